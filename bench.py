@@ -1,0 +1,207 @@
+#!/usr/bin/env python
+"""Throughput of the ImEx-ARK stage cycle of the pseudospectral phase-field method.
+
+Workload: the 512^3 precision-form configuration (about 1600 seeded spherical
+nuclei of radius 2-5, spacing 8, c0 = 0.16 +- 0.005) advanced by fixed-step
+ARK4(3)6L (6 explicit RHS stages per step), first in FP64 (`value`), then
+with FP32 FFT/pointwise/elastic work and FP64 stage sums (`mixed`).  A step
+is one full pass of the hot path: six stage-combine + implicit-solve +
+explicit-RHS cycles and the update / embedded-error / WRMS finalize.  Inputs
+are resident on the GPU before timing starts.
+
+Prints ONE JSON line.  Extra objects:
+  roofline      dominant kernel's algorithmic bytes per launch / average
+                launch time (HIP events around each launch on the library's
+                stream, inside the timed region) against 8 TB/s HBM;
+  kernels       the same for every kernel class;
+  mixed         the mixed-precision run of the same workload;
+  fft           standalone forward + inverse 3D real FFT of 4 fields (FP64);
+  cpu_baseline  the FP64 CPU oracle on a bounded sample (one ARK4 step at
+                128^3 of the same seeded generator), one thread.
+"""
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "Mpts·stages/s at 512^3 (FP64 vs FP32-mixed); FFT HBM GB/s; time-to-t at tol"
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def kernel_table(rep):
+    out = {}
+    for name, (ms, n, b) in rep.items():
+        avg_ms = ms / n
+        gbs = (b / n) / (avg_ms * 1e-3) / 1e9
+        out[name] = dict(launches=n, avg_ms=round(avg_ms, 4), total_ms=round(ms, 3),
+                         bytes_per_launch=b / n, gbs=round(gbs, 1),
+                         frac=round(gbs / HBM_PEAK_GBS, 4))
+    return out
+
+
+def run_solver(torch, n, c, eta, precision, steps, warmup, dt):
+    from paper_2609_36100_amd import Solver
+    s = Solver(n, None, method="ark436l", precision=precision, dt0=dt)
+    s.set_state(c, eta)
+    for _ in range(warmup):
+        acc, _, _ = s.step(dt)
+        assert acc
+    torch.cuda.synchronize()
+    s.profile(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        acc, err, _ = s.step(dt)
+        assert acc
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    rep = s.profile_report()
+    s.profile(False)
+    st = s.stats()
+    s.close()
+    wall = t1 - t0
+    stages = 6 * steps
+    return dict(value=n ** 3 * stages / wall / 1e6, ms_per_step=1e3 * wall / steps,
+                kernels=kernel_table(rep), n_rhs=st["n_rhs"], err_last=err)
+
+
+def fft_bench(torch, n, reps=3):
+    from paper_2609_36100_amd import Solver
+    s = Solver(n, None)
+    u = torch.randn((4, n, n, n), dtype=torch.float64, device="cuda")
+    k = s.kspace_empty(4)
+    back = torch.empty_like(u)
+    s.fft3d(-1, 4, u, k)
+    s.fft3d(+1, 4, k, back)
+    torch.cuda.synchronize()
+    s.profile(True)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        s.fft3d(-1, 4, u, k)
+        s.fft3d(+1, 4, k, back)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / reps
+    rep = s.profile_report()
+    s.close()
+    tab = kernel_table(rep)
+    tot_ms = sum(v[0] for v in rep.values()) / reps
+    tot_b = sum(v[2] for v in rep.values()) / reps
+    real_b = 4 * n ** 3 * 8.0
+    return dict(fields=4, n=n, precision="f64", ms_fwd_inv=round(1e3 * wall, 3),
+                pass_gbs=round(tot_b / (tot_ms * 1e-3) / 1e9, 1),
+                pass_frac=round(tot_b / (tot_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                effective_gbs_1r1w=round(2 * 2 * real_b / wall / 1e9, 1),
+                kernels=tab)
+
+
+def cpu_baseline(n=128):
+    """The FP64 oracle, as it stands, on one ARK4(3)6L step at n^3 (single thread)."""
+    import numpy as np  # noqa: F401
+    import pfinputs
+    from oracle import ark as oark
+    from oracle import model as om
+    spec, c, eta = pfinputs.config("mixed512", n=n)
+    m = om.Model((n, n, n), pfinputs.default_params())
+    m.B()  # one-time per-grid setup, not part of a step
+    y = om.to_kspace(c, eta)
+    L = m.implicit_symbol()
+    t0 = time.perf_counter()
+    _, _, nexp = oark.ark_step(y, 0.1, oark.ark436l2sa(), m.f_explicit, L)
+    wall = time.perf_counter() - t0
+    return dict(value=round(n ** 3 * nexp / wall / 1e6, 4), unit="Mpts·stages/s", cores=1,
+                kind="oracle",
+                sample="one ARK4(3)6L step (6 stages) of the NumPy FP64 oracle at %d^3, same seeded "
+                       "generator with the nucleus count scaled by volume; pocketfft, one thread; "
+                       "%.1f s; host %s" % (n, wall, platform.processor() or platform.machine()))
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=512)
+    ap.add_argument("--dt", type=float, default=0.1)
+    ap.add_argument("--skip-mixed", action="store_true")
+    ap.add_argument("--skip-fft", action="store_true")
+    ap.add_argument("--skip-cpu", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: the stage cycle runs on a single MI355X; "
+              "--gpus %d is not supported" % max(args.gpus, world), file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import pfinputs
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    n = args.n
+    log("generating %d^3 seeded initial condition" % n)
+    spec, c, eta = pfinputs.config("mixed512", n=n)
+    ct = torch.from_numpy(c).cuda()
+    et = torch.from_numpy(eta).cuda()
+    del c, eta
+
+    log("FP64 run: %d warmup + %d timed ARK4 steps" % (args.warmup, args.steps))
+    r64 = run_solver(torch, n, ct, et, "fp64", args.steps, args.warmup, args.dt)
+    log("FP64 %.1f Mpts*stages/s, %.1f ms/step" % (r64["value"], r64["ms_per_step"]))
+    mixed = None
+    if not args.skip_mixed:
+        log("mixed run")
+        rm = run_solver(torch, n, ct, et, "mixed", args.steps, args.warmup, args.dt)
+        log("mixed %.1f Mpts*stages/s, %.1f ms/step" % (rm["value"], rm["ms_per_step"]))
+        mixed = dict(value=round(rm["value"], 2), ms_per_step=round(rm["ms_per_step"], 3),
+                     dtype="f32 FFT/pointwise/elastic, f64 stage sums and error", kernels=rm["kernels"],
+                     speedup_vs_fp64=round(rm["value"] / r64["value"], 3))
+    del ct, et
+    torch.cuda.empty_cache()
+    fft = None
+    if not args.skip_fft:
+        log("FFT run")
+        fft = fft_bench(torch, n)
+    kt = r64["kernels"]
+    dom = max(kt, key=lambda k: kt[k]["total_ms"])
+    d = kt[dom]
+    roofline = dict(bound="hbm", kernel=dom, achieved=d["gbs"], peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=d["frac"], traffic=None)
+    cpu = None
+    if not args.skip_cpu:
+        log("CPU oracle sample")
+        cpu = cpu_baseline()
+    line = {
+        "metric": METRIC,
+        "value": round(r64["value"], 2),
+        "unit": "Mpts·stages/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(r64["ms_per_step"], 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "%d^3 ARK4(3)6L fixed dt=%g, %d seeded nuclei (radius 2-5, spacing 8), "
+                               "6 stages per step" % (n, args.dt, spec["n_nuclei"]),
+                   "grid": n, "stages_per_step": 6, "dt": args.dt},
+        "roofline": roofline,
+        "kernels": kt,
+        "mixed": mixed,
+        "fft": fft,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

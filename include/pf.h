@@ -1,0 +1,200 @@
+/* libpf: pseudospectral phase-field ImEx-ARK hot path for MI355X (gfx950).
+ *
+ * The library advances the state vector y = (c, eta_1, eta_2, eta_3) of one
+ * Cahn-Hilliard composition and three Allen-Cahn order parameters, coupled by
+ * homogeneous-modulus (Khachaturyan) elasticity on a periodic 3D grid, with
+ * additive ImEx Runge-Kutta methods.  It follows the paper's statement of the
+ * problem: the ImEx ODE y' = f^I(t,y) + f^E(t,y) in reciprocal space
+ * (Methods, "Time integration", Eq. imex_ode), stiff linear terms implicit and
+ * solved per wavevector (Eqs. composition, order), the stage and update
+ * formulas of Eq. ARK_method, the embedded error of Eq. ARK_embedding and the
+ * WRMS acceptance test of Eqs. wrms_norm / wrms_weights.
+ *
+ * Conventions (every entry point):
+ *  - Real-space fields are float64, C order [z][y][x] (x fastest);
+ *    eta is stacked [3][z][y][x].
+ *  - Reciprocal-space arrays are complex128 (interleaved re, im), layout
+ *    [4][nz][ny][kp] with kp = pf_kspace_pitch(ctx) >= nx/2 + 1; entries with
+ *    kx >= nx/2 + 1 are padding (ignored on input, undefined on output).
+ *    Field order c, eta_1, eta_2, eta_3.  Forward transform unnormalised,
+ *    u~(k) = sum_r u(r) exp(-i k.r), k_i = 2 pi m_i / (N_i dx).
+ *  - Pointers marked "device" must be device memory of the GPU current at
+ *    pf_init; pointers marked "host or device" are selected by on_device.
+ *    The caller owns every pointer it passes; libpf owns its workspace and
+ *    frees it in pf_finalize.
+ *  - All work is ordered on the HIP stream given to pf_init (NULL = default
+ *    stream).  Entry points that return host values synchronise that stream.
+ *  - Errors are returned as pf_status codes; nothing is thrown across the
+ *    ABI.  A context is not thread-safe.
+ */
+#ifndef PF_H_
+#define PF_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pf_ctx pf_ctx;
+
+typedef enum {
+  PF_OK = 0,
+  PF_ERR_ARG = -1,              /* invalid argument or parameter */
+  PF_ERR_OOM = -2,              /* device allocation failed */
+  PF_ERR_HIP = -3,              /* a HIP runtime call failed */
+  PF_ERR_UNSUPPORTED_SIZE = -4, /* grid size not in the supported set */
+  PF_ERR_STEP_FAIL = -5,        /* too many consecutive rejected steps */
+  PF_ERR_NONFINITE = -6,        /* a step produced NaN/Inf (state unchanged) */
+  PF_ERR_STATE = -7             /* call not valid in the context's state */
+} pf_status;
+
+typedef enum { PF_FP64 = 0, PF_MIXED = 1 } pf_precision;
+
+typedef enum { PF_IMEX_EULER = 1, PF_ARK436L = 4 } pf_method;
+
+/* Model, discretisation and integrator parameters.
+ * Model (Methods, "Phase-field model formulation", dimensionless stand-in):
+ *   f = W (c-c_m)^2 (1-H) + W (c-c_p)^2 H + w sum_v eta_v^2 (1-eta_v)^2,
+ *   H = sum_v h(eta_v), h(e) = e^3 (6e^2 - 15e + 10),
+ *   gradient energy kappa_c/2 |grad c|^2 + kappa_eta/2 sum_v |grad eta_v|^2,
+ *   elastic energy with cubic stiffness (C11, C12, C44) and the diagonal
+ *   eigenstrain eps_star[v][axis] of variant v (mechanical equilibrium,
+ *   Eq. u_gov, with one stiffness for all phases, solved per wavevector).
+ *   dc/dt = div(M grad dF/dc) (Eq. x_gov), deta_v/dt = -L dF/deta_v (Eq. phi_gov).
+ * Split: f^I_c = -M k^2 (a_c + kappa_c k^2) c~ with a_c = 2W when
+ *   implicit_bulk_c = 1 (default) else 0; f^I_eta = -L kappa_eta k^2 eta~.
+ * Sizes: nx, ny, nz must each be a multiple of 8 with no prime factor above
+ *   5, between 8 and 512 (see pf_size_supported). */
+typedef struct {
+  int32_t nx, ny, nz;
+  double dx;
+  double W, w, kappa_c, kappa_eta, M, L, c_m, c_p;
+  double C11, C12, C44;
+  double eps_star[3][3];    /* [variant][axis x,y,z], diagonal eigenstrains */
+  double eps_bar[3];        /* prescribed diagonal mean strain (mode 0) */
+  int32_t mean_strain_mode; /* 0: prescribed eps_bar, 1: stress-free */
+  int32_t implicit_bulk_c;  /* 1: 2W k^2 implicit (default), 0: explicit */
+  int32_t precision;        /* pf_precision */
+  int32_t method;           /* pf_method */
+  int32_t adaptive;         /* 1: embedded-error step control (ARK436L only) */
+  double dt0, rtol, atol, dt_min, dt_max;
+  int32_t max_rejects;      /* consecutive rejections before PF_ERR_STEP_FAIL */
+} pf_params;
+
+typedef struct {
+  int64_t steps;       /* accepted steps */
+  int64_t attempts;    /* attempted steps */
+  int64_t rejects;     /* rejected attempts */
+  int64_t n_rhs;       /* explicit RHS evaluations */
+  double t;            /* current time */
+  double dt_last;      /* last accepted step size */
+  double dt_next;      /* proposed next step size */
+  double dt_min_seen, dt_max_seen;
+  double err_last;     /* WRMS error estimate of the last attempt */
+  double mass;         /* mean of c (k = 0 coefficient / N^3) */
+  double elapsed_ms;   /* device time spent in pf_advance / pf_ark_step */
+} pf_stats;
+
+/* Fills p with the defaults of the stand-in model: W=w=kappa=M=L=1,
+ * c_m=0.02, c_p=0.25, C=(250,150,120), eigenstrain 0.0286 along the variant
+ * axis and 0.0067 on the others, dx=1, ARK4(3)6L, FP64, fixed step 1e-2.
+ * Never fails for non-NULL p. */
+pf_status pf_default_params(pf_params* p);
+
+/* Returns 1 if n is a supported grid length, else 0. */
+int32_t pf_size_supported(int32_t n);
+
+/* Creates a context for the grid and model in *p on the current device and
+ * allocates its workspace (state, stage arrays, FFT temporaries).
+ * hip_stream: a hipStream_t or NULL.  On success *out owns the workspace.
+ * Errors: PF_ERR_ARG (bad parameter), PF_ERR_UNSUPPORTED_SIZE, PF_ERR_OOM. */
+pf_status pf_init(const pf_params* p, void* hip_stream, pf_ctx** out);
+
+/* Frees the context and its workspace (NULL is a no-op). */
+void pf_finalize(pf_ctx* ctx);
+
+/* Row pitch kp (complex elements) of every reciprocal-space array. */
+int64_t pf_kspace_pitch(const pf_ctx* ctx);
+
+/* Bytes of device workspace the context holds. */
+int64_t pf_workspace_bytes(const pf_ctx* ctx);
+
+/* Sets the state from real-space fields (transformed to reciprocal space).
+ * c: N = nz*ny*nx values; eta: 3N values; host or device per on_device.
+ * Resets t to t0. */
+pf_status pf_set_state(pf_ctx* ctx, const double* c, const double* eta,
+                       int32_t on_device, double t0);
+
+/* Writes the real-space state into c (N values) and eta (3N values), host or
+ * device per on_device (inverse transform of the reciprocal-space state). */
+pf_status pf_get_state(pf_ctx* ctx, double* c, double* eta, int32_t on_device);
+
+/* Copies the reciprocal-space state to / from device memory y_hat
+ * (layout above). */
+pf_status pf_get_state_hat(pf_ctx* ctx, void* y_hat_device);
+pf_status pf_set_state_hat(pf_ctx* ctx, const void* y_hat_device, double t0);
+
+/* One evaluation of the split right-hand side at the reciprocal-space state
+ * y_hat (device, read only): fI_hat = f^I(y), fE_hat = f^E(y) (device,
+ * written).  Autonomous: t is accepted for interface symmetry.  This is the
+ * stage right-hand side of Eq. ARK_stage: inverse 3D FFT of the state,
+ * pointwise driving forces, forward FFT of h(eta_v), per-wavevector elastic
+ * solve, inverse FFT of the elastic potentials, forward FFT of the AC
+ * driving forces.  Does not change the context's state. */
+pf_status pf_rhs(pf_ctx* ctx, double t, const void* y_hat, void* fI_hat, void* fE_hat);
+
+/* Attempts one step of size dt from the current state (Eq. ARK_method).
+ * With adaptive control the step is accepted iff the WRMS norm of the
+ * embedded error estimate is <= 1; otherwise always (if finite).  On
+ * acceptance the state and t advance.  Outputs (any may be NULL): the
+ * controller's next step size, the WRMS error (0 without embedding) and the
+ * acceptance flag.  Returns PF_ERR_NONFINITE (state unchanged) if the
+ * attempt produced NaN/Inf in a fixed-step run. */
+pf_status pf_ark_step(pf_ctx* ctx, double dt, double* dt_next, double* err_wrms,
+                      int32_t* accepted);
+
+/* Advances to t_final: fixed steps of dt0 or the adaptive controller, the
+ * last step clipped to land on t_final.  Fills *out if non-NULL.
+ * PF_ERR_STEP_FAIL after max_rejects consecutive rejections. */
+pf_status pf_advance(pf_ctx* ctx, double t_final, pf_stats* out);
+
+pf_status pf_get_stats(pf_ctx* ctx, pf_stats* out);
+
+/* Current time and the proposed next step size. */
+double pf_get_time(const pf_ctx* ctx);
+pf_status pf_set_dt(pf_ctx* ctx, double dt);
+
+/* Mean of c, mean of H = sum_v h(eta_v) (precipitate volume fraction) and the
+ * fraction of points with max_v eta_v > 0.5, from the current state. */
+pf_status pf_diagnostics(pf_ctx* ctx, double* mass, double* vf, double* vf_threshold);
+
+/* Standalone 3D real FFT of nf fields (the transform every stage uses).
+ * dir = -1: real [nf][nz][ny][nx] -> reciprocal [nf][nz][ny][kp] (unnormalised);
+ * dir = +1: reciprocal -> real, scaled by 1/(nx ny nz).
+ * in/out: device; nf in 1..4; in and out must not overlap.  The inverse
+ * overwrites `in` (it is used as the intermediate). */
+pf_status pf_fft3d(pf_ctx* ctx, int32_t dir, int32_t nf, void* in, void* out);
+
+/* Per-kernel-class timing with HIP events on the context's stream.
+ * pf_profile_enable(ctx, on) clears the counters and turns recording on/off.
+ * Classes 0 .. pf_profile_classes()-1 are named by pf_profile_name (never
+ * NULL; "" for an invalid class).  pf_profile_get returns the summed device
+ * milliseconds, the number of launches and the summed algorithmic bytes
+ * (bytes each launch must read and write once: valid half-spectrum entries
+ * of every array it touches) of a class.  Intended for measurement, not for
+ * use under graph capture. */
+pf_status pf_profile_enable(pf_ctx* ctx, int32_t on);
+int32_t pf_profile_classes(void);
+const char* pf_profile_name(int32_t cls);
+pf_status pf_profile_get(pf_ctx* ctx, int32_t cls, double* total_ms, int64_t* launches, double* bytes);
+
+/* Human-readable status name; never NULL. */
+const char* pf_status_string(pf_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PF_H_ */

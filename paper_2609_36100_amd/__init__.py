@@ -1,0 +1,182 @@
+"""MI355X-native pseudospectral phase-field ImEx-ARK hot path (Python front end).
+
+The compute path lives in ``libpf.so`` (HIP kernels for gfx950 behind the C ABI
+of ``include/pf.h``).  This package is a thin binding: :class:`Solver` owns a
+``pf_ctx`` and marshals PyTorch device tensors and numpy arrays to it.  There
+is no CPU fallback: without the built library, creating a solver raises.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from . import _lib
+from ._lib import PFError, Stats, make_params  # noqa: F401
+
+__all__ = ["Solver", "PFError", "make_params", "size_supported", "fft3d"]
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def size_supported(n):
+    return bool(_lib.lib().pf_size_supported(int(n)))
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Solver:
+    """One simulation context on the current GPU.
+
+    Parameters mirror ``pf_params``: ``n`` (int or (nx, ny, nz)), ``model``
+    (dict of model constants, see ``pfinputs.default_params``), ``method``
+    ("imex_euler" | "ark436l"), ``precision`` ("fp64" | "mixed"), ``adaptive``,
+    ``dt0``, ``rtol``, ``atol``.
+    """
+
+    def __init__(self, n, model=None, stream=None, **kw):
+        torch = _torch()
+        if not torch.cuda.is_available():
+            raise RuntimeError("libpf needs a GPU (gfx950); none is visible")
+        L = _lib.lib()
+        self.params = make_params(n, model, **kw)
+        self.shape = (self.params.nz, self.params.ny, self.params.nx)
+        self._stream = stream if stream is not None else torch.cuda.current_stream()
+        h = ctypes.c_void_p()
+        _lib.check(L.pf_init(ctypes.byref(self.params), ctypes.c_void_p(self._stream.cuda_stream),
+                             ctypes.byref(h)), "pf_init")
+        self._h = h
+        self.kpitch = int(L.pf_kspace_pitch(h))
+        self.nxh = self.params.nx // 2 + 1
+
+    # -- lifetime ---------------------------------------------------------
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.lib().pf_finalize(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # -- buffers ------------------------------------------------------------
+    def kspace_empty(self, nf=4):
+        torch = _torch()
+        nz, ny, _ = self.shape
+        return torch.empty((nf, nz, ny, self.kpitch), dtype=torch.complex128, device="cuda")
+
+    def kspace_from_numpy(self, a):
+        """Pad a (nf, nz, ny, nx//2+1) complex array to the library pitch on the GPU."""
+        torch = _torch()
+        t = self.kspace_empty(a.shape[0])
+        t.zero_()
+        t[..., : self.nxh] = torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+        return t
+
+    def kspace_to_numpy(self, t):
+        return t[..., : self.nxh].cpu().numpy()
+
+    @property
+    def workspace_bytes(self):
+        return int(_lib.lib().pf_workspace_bytes(self._h))
+
+    # -- state ----------------------------------------------------------------
+    def set_state(self, c, eta, t0=0.0):
+        torch = _torch()
+        if isinstance(c, torch.Tensor):
+            c = c.to(device="cuda", dtype=torch.float64).contiguous()
+            eta = eta.to(device="cuda", dtype=torch.float64).contiguous()
+            _lib.check(_lib.lib().pf_set_state(self._h, _ptr(c), _ptr(eta), 1, float(t0)), "pf_set_state")
+        else:
+            c = np.ascontiguousarray(c, dtype=np.float64)
+            eta = np.ascontiguousarray(eta, dtype=np.float64)
+            assert c.shape == self.shape and eta.shape == (3,) + self.shape
+            _lib.check(_lib.lib().pf_set_state(self._h, c.ctypes.data_as(ctypes.c_void_p),
+                                               eta.ctypes.data_as(ctypes.c_void_p), 0, float(t0)),
+                       "pf_set_state")
+
+    def get_state(self):
+        c = np.empty(self.shape)
+        eta = np.empty((3,) + self.shape)
+        _lib.check(_lib.lib().pf_get_state(self._h, c.ctypes.data_as(ctypes.c_void_p),
+                                           eta.ctypes.data_as(ctypes.c_void_p), 0), "pf_get_state")
+        return c, eta
+
+    def get_state_hat(self):
+        t = self.kspace_empty()
+        _lib.check(_lib.lib().pf_get_state_hat(self._h, _ptr(t)), "pf_get_state_hat")
+        return t
+
+    def set_state_hat(self, t, t0=0.0):
+        _lib.check(_lib.lib().pf_set_state_hat(self._h, _ptr(t.contiguous()), float(t0)), "pf_set_state_hat")
+
+    # -- hot path -------------------------------------------------------------
+    def rhs(self, y_hat, t=0.0):
+        fI = self.kspace_empty()
+        fE = self.kspace_empty()
+        _lib.check(_lib.lib().pf_rhs(self._h, float(t), _ptr(y_hat), _ptr(fI), _ptr(fE)), "pf_rhs")
+        return fI, fE
+
+    def step(self, dt):
+        dn, err, acc = ctypes.c_double(), ctypes.c_double(), ctypes.c_int32()
+        code = _lib.lib().pf_ark_step(self._h, float(dt), ctypes.byref(dn), ctypes.byref(err),
+                                      ctypes.byref(acc))
+        _lib.check(code, "pf_ark_step")
+        return bool(acc.value), err.value, dn.value
+
+    def advance(self, t_final):
+        st = Stats()
+        _lib.check(_lib.lib().pf_advance(self._h, float(t_final), ctypes.byref(st)), "pf_advance")
+        return st.as_dict()
+
+    def stats(self):
+        st = Stats()
+        _lib.check(_lib.lib().pf_get_stats(self._h, ctypes.byref(st)), "pf_get_stats")
+        return st.as_dict()
+
+    @property
+    def t(self):
+        return float(_lib.lib().pf_get_time(self._h))
+
+    def set_dt(self, dt):
+        _lib.check(_lib.lib().pf_set_dt(self._h, float(dt)), "pf_set_dt")
+
+    def diagnostics(self):
+        m, v, vt = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        _lib.check(_lib.lib().pf_diagnostics(self._h, ctypes.byref(m), ctypes.byref(v), ctypes.byref(vt)),
+                   "pf_diagnostics")
+        return dict(mass=m.value, vf=v.value, vf_threshold=vt.value)
+
+    # -- measurement ----------------------------------------------------------
+    def profile(self, on=True):
+        """Clear and enable/disable per-kernel-class HIP-event timing."""
+        _lib.check(_lib.lib().pf_profile_enable(self._h, 1 if on else 0), "pf_profile_enable")
+
+    def profile_report(self):
+        """{class: (total_ms, launches, algorithmic_bytes)} for classes with launches."""
+        L = _lib.lib()
+        out = {}
+        for k in range(L.pf_profile_classes()):
+            ms, n, b = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double()
+            _lib.check(L.pf_profile_get(self._h, k, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(b)),
+                       "pf_profile_get")
+            if n.value:
+                out[L.pf_profile_name(k).decode()] = (ms.value, n.value, b.value)
+        return out
+
+    def fft3d(self, direction, nf, src, dst):
+        """Standalone 3D real FFT on device tensors (see pf_fft3d)."""
+        _lib.check(_lib.lib().pf_fft3d(self._h, int(direction), int(nf), _ptr(src), _ptr(dst)), "pf_fft3d")

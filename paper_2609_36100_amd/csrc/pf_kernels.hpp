@@ -1,0 +1,716 @@
+// HIP kernels of one ImEx-ARK stage for the pseudospectral phase-field model.
+//
+// A stage (Methods, "Time integration", Eq. ARK_stage, with the right-hand
+// side of Eqs. composition / order) is nine HBM-streaming passes over the
+// half spectrum [field][z][y][kx] (row pitch P complex values):
+//
+//  stage_invz    combine previous stage derivatives, implicit solve per mode,
+//                F^I = L z, inverse z-FFT of the 4 state fields      (z pass)
+//  ypass<+1>     inverse y-FFT of the 4 state fields                   (y pass)
+//  xpass_theta   c2r of eta_v, theta_v = h(eta_v), r2c of theta_v      (x pass)
+//  ypass<-1>     forward y-FFT of theta                                (y pass)
+//  zpass_elastic forward z-FFT, per-mode elastic solve e~ = B(n) theta~,
+//                explicit CH term, inverse z-FFT of e~                 (z pass)
+//  ypass<+1>     inverse y-FFT of e~                                   (y pass)
+//  xpass_drive   c2r of c, eta_v, e_v, driving force, r2c              (x pass)
+//  ypass<-1>     forward y-FFT of the driving force                    (y pass)
+//  zpass_fwd_ac  forward z-FFT, F^E_eta = -L g~                        (z pass)
+//
+// followed once per step by `finalize` (update, embedded error, WRMS partial
+// sums).  z and y passes give each work-group TX consecutive kx columns of one
+// plane so every global access is TX contiguous complex values; x passes give
+// each work-group RB whole rows.  Line FFTs run in LDS with Stockham passes;
+// inputs and outputs of a line stay in registers so the pointwise and
+// per-mode work happens between the transforms without extra HBM traffic.
+#pragma once
+
+#include "pf_fft.hpp"
+
+namespace pf {
+
+// ---- geometry and model constants -----------------------------------------
+struct Geo {
+  int nx, ny, nz, nxh, P;
+  long long fs;          // complex elements per field = nz * ny * P
+  double kfx, kfy, kfz;  // 2 pi / (N_i dx)
+};
+
+struct ModelK {
+  double M, L, kc, ke, ac;  // mobilities, gradient coefficients, implicit bulk
+  double W, w, cm, cp;
+  double fEc;               // 2 W M (c_p - c_m): explicit CH coefficient (split B)
+  double fEa;               // (2W - a_c) M: extra explicit CH coefficient (split A)
+  double E[3][3];           // eps*_v : C : eps*_w
+  double B0[3][3];          // k = 0 kernel (E or 0)
+  double S[3][3];           // diagonal of sigma*_v = C : eps*_v, [v][axis]
+  double C11, C12, C44;
+  double hom[3];            // N^3 * (-eps*_v : C : eps_bar), added to e~_v(0)
+  double inv_n3;            // 1 / (nx ny nz)
+};
+
+__host__ __device__ inline int mode_of(int i, int n) { return (2 * i < n) ? i : i - n; }
+
+// Implicit symbol L_f(k^2) for field f (0 = c, 1..3 = eta).
+__device__ inline double lsym(const ModelK& m, int f, double k2) {
+  return f == 0 ? -m.M * k2 * (m.ac + m.kc * k2) : -m.L * m.ke * k2;
+}
+
+// Khachaturyan kernel contraction e_v = sum_w B_vw(k) th_w for k != 0:
+// B_vw = E_vw - (S_v k) . Omega(k) . (S_w k),  Omega(k)^-1 = C_ijkl k_j k_l.
+// Uses k directly (Omega scales as 1/|k|^2, S k as |k|): no normalisation.
+template <typename R>
+__device__ inline void elastic_apply(const ModelK& m, R kx, R ky, R kz, const cx<R>* th, cx<R>* e) {
+  const R C11 = (R)m.C11, C12 = (R)m.C12, C44 = (R)m.C44;
+  const R a = C11 - C12 - (R)2 * C44;
+  const R b = C12 + C44;
+  const R k2 = kx * kx + ky * ky + kz * kz;
+  // Omega^-1 (symmetric): C44 k^2 d_ik + b k_i k_k + a k_i^2 d_ik
+  const R g00 = C44 * k2 + (b + a) * kx * kx;
+  const R g11 = C44 * k2 + (b + a) * ky * ky;
+  const R g22 = C44 * k2 + (b + a) * kz * kz;
+  const R g01 = b * kx * ky, g02 = b * kx * kz, g12 = b * ky * kz;
+  // adjugate
+  const R A00 = g11 * g22 - g12 * g12;
+  const R A11 = g00 * g22 - g02 * g02;
+  const R A22 = g00 * g11 - g01 * g01;
+  const R A01 = g02 * g12 - g01 * g22;
+  const R A02 = g01 * g12 - g02 * g11;
+  const R A12 = g01 * g02 - g00 * g12;
+  const R det = g00 * A00 + g01 * A01 + g02 * A02;
+  const R idet = (R)1 / det;
+  R s[3][3];  // s_v = S_v k  (componentwise)
+  R u[3][3];  // u_v = adj * s_v
+#pragma unroll
+  for (int v = 0; v < 3; ++v) {
+    s[v][0] = (R)m.S[v][0] * kx;
+    s[v][1] = (R)m.S[v][1] * ky;
+    s[v][2] = (R)m.S[v][2] * kz;
+    u[v][0] = A00 * s[v][0] + A01 * s[v][1] + A02 * s[v][2];
+    u[v][1] = A01 * s[v][0] + A11 * s[v][1] + A12 * s[v][2];
+    u[v][2] = A02 * s[v][0] + A12 * s[v][1] + A22 * s[v][2];
+  }
+#pragma unroll
+  for (int v = 0; v < 3; ++v) {
+    cx<R> acc = mk<R>(0, 0);
+#pragma unroll
+    for (int w = 0; w < 3; ++w) {
+      const R q = (s[w][0] * u[v][0] + s[w][1] * u[v][1] + s[w][2] * u[v][2]) * idet;
+      const R bvw = (R)m.E[v][w] - q;
+      acc = acc + bvw * th[w];
+    }
+    e[v] = acc;
+  }
+}
+
+// ---- line FFT in LDS -------------------------------------------------------
+__host__ __device__ constexpr int plan_prod(int n, int q) {
+  Plan P = plan(n);
+  int p = 1;
+  for (int i = 0; i < q; ++i) p *= P.r[i];
+  return p;
+}
+
+template <typename T, int N, int S, int Q>
+struct MidPass {
+  template <class Buf>
+  __device__ static inline void run(int tid, const cx<T>* tw, Buf buf) {
+    constexpr Plan PL = plan(N);
+    if constexpr (Q < PL.np - 1) {
+      constexpr int r = PL.r[Q];
+      constexpr int p = plan_prod(N, Q);
+      constexpr int TL = N / PL.r[0];
+      constexpr int NB = N / r;
+      constexpr int PER = (NB + TL - 1) / TL;
+      cx<T> v[PER][r];
+#pragma unroll
+      for (int j = 0; j < PER; ++j) {
+        const int b = tid + j * TL;
+        if (PER * TL == NB || b < NB) {
+          const int k = b % p;
+#pragma unroll
+          for (int t = 0; t < r; ++t) v[j][t] = buf(b + t * NB);
+          constexpr int step = N / (p * r);
+#pragma unroll
+          for (int t = 1; t < r; ++t) v[j][t] = cmul(v[j][t], twiddle<S>(tw, t * k * step));
+          dft<r, S>(v[j]);
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int j = 0; j < PER; ++j) {
+        const int b = tid + j * TL;
+        if (PER * TL == NB || b < NB) {
+          const int k = b % p;
+#pragma unroll
+          for (int t = 0; t < r; ++t) buf((b - k) * r + k + t * p) = v[j][t];
+        }
+      }
+      __syncthreads();
+      MidPass<T, N, S, Q + 1>::run(tid, tw, buf);
+    }
+  }
+};
+
+// In-place FFT of one line of length N by TL = N / r0 cooperating threads.
+// On entry a[t] holds x[tid + t N/r0]; on exit X[tid + t N/r0].  Every thread
+// of the work-group must call this the same number of times (it contains
+// work-group barriers); the LDS region behind `buf` must hold N values.
+template <typename T, int N, int S, class Buf>
+__device__ inline void line_fft(cx<T>* a, int tid, const cx<T>* tw, Buf buf) {
+  constexpr Plan PL = plan(N);
+  static_assert(PL.ok, "unsupported line length");
+  constexpr int R0 = PL.r[0];
+  constexpr int TL = N / R0;
+  dft<R0, S>(a);
+  if constexpr (PL.np > 1) {
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < R0; ++t) buf(tid * R0 + t) = a[t];
+    __syncthreads();
+    MidPass<T, N, S, 1>::run(tid, tw, buf);
+#pragma unroll
+    for (int t = 0; t < R0; ++t) a[t] = buf(tid + t * TL);
+    // last pass: p = N / R0, k = tid, twiddle w_N^{t tid}
+#pragma unroll
+    for (int t = 1; t < R0; ++t) a[t] = cmul(a[t], twiddle<S>(tw, t * tid));
+    dft<R0, S>(a);
+  }
+}
+
+template <typename T>
+__device__ inline cx<T> ld(const cx<T>* p) { return *p; }
+
+template <typename T>
+__device__ inline cx<T> to_t(cx<double> z) { return mk<T>((T)z.re, (T)z.im); }
+template <typename T>
+__device__ inline cx<double> to_d(cx<T> z) { return mk<double>((double)z.re, (double)z.im); }
+
+// ---- column-pass geometry -----------------------------------------------
+template <int N, int TX>
+struct ColGeo {
+  static constexpr int R0 = plan(N).r[0];
+  static constexpr int TL = N / R0;
+  static constexpr int THREADS = TX * TL;
+  static constexpr int LD = TX + 1;  // LDS row pitch (padding)
+};
+
+// ---- K-A: stage combine + implicit solve + inverse z-FFT -------------------
+template <typename TE>
+struct StageArgs {
+  const cx<double>* y;
+  const cx<TE>* FE[6];
+  const cx<double>* FI[6];
+  double cE[6], cI[6];     // dt * A^E_ij, dt * A^I_ij for j < i
+  int nprev;
+  double gdt;              // dt * A^I_ii
+  cx<double>* FI_out;      // F^I_i (may be null when unused)
+  cx<TE>* FEc_out;         // split A: explicit CH part from z_c (may be null)
+};
+
+template <typename T, typename TE, int N, int TX>
+__global__ void __launch_bounds__((ColGeo<N, TX>::THREADS))
+k_stage_invz(StageArgs<TE> sa, Geo g, ModelK m, const cx<T>* __restrict__ twz,
+             cx<T>* __restrict__ out, int do_fft) {
+  using CG = ColGeo<N, TX>;
+  __shared__ cx<T> lds[N * CG::LD];
+  const int nbx = (g.nxh + TX - 1) / TX;
+  const int xb = blockIdx.x % nbx;
+  const int y = blockIdx.x / nbx;
+  const int col = threadIdx.x % TX;
+  const int bf = threadIdx.x / TX;
+  const int x = xb * TX + col;
+  const bool valid = x < g.nxh;
+  const double kx = x * g.kfx;
+  const double ky = mode_of(y, g.ny) * g.kfy;
+  auto buf = [&](int pos) -> cx<T>& { return lds[pos * CG::LD + col]; };
+  for (int f = 0; f < 4; ++f) {
+    cx<T> a[CG::R0];
+#pragma unroll
+    for (int t = 0; t < CG::R0; ++t) {
+      const int z = bf + t * CG::TL;
+      const long long idx = f * g.fs + ((long long)z * g.ny + y) * g.P + x;
+      cx<double> r = mk(0.0, 0.0);
+      if (valid) {
+        r = sa.y[idx];
+        for (int j = 0; j < sa.nprev; ++j) {
+          if (sa.cE[j] != 0.0) r = r + sa.cE[j] * to_d(sa.FE[j][idx]);
+          if (sa.cI[j] != 0.0) r = r + sa.cI[j] * sa.FI[j][idx];
+        }
+        const double kz = mode_of(z, g.nz) * g.kfz;
+        const double k2 = kx * kx + ky * ky + kz * kz;
+        const double L = lsym(m, f, k2);
+        const cx<double> zz = (sa.gdt != 0.0) ? (1.0 / (1.0 - sa.gdt * L)) * r : r;
+        if (sa.FI_out) sa.FI_out[idx] = L * zz;
+        if (f == 0 && sa.FEc_out) sa.FEc_out[idx] = to_t<TE>((-m.fEa * k2) * zz);
+        r = m.inv_n3 * zz;
+      }
+      a[t] = to_t<T>(r);
+    }
+    if (do_fft) {
+      line_fft<T, N, +1>(a, bf, twz, buf);
+      if (valid) {
+#pragma unroll
+        for (int t = 0; t < CG::R0; ++t) {
+          const int z = bf + t * CG::TL;
+          out[f * g.fs + ((long long)z * g.ny + y) * g.P + x] = a[t];
+        }
+      }
+    }
+  }
+}
+
+// ---- generic column FFT along y or z (in or out of place) -----------------
+// axis 1 = y (lines at fixed z), axis 2 = z (lines at fixed y).
+template <typename T, int N, int TX, int S, int AXIS>
+__global__ void __launch_bounds__((ColGeo<N, TX>::THREADS))
+k_colfft(const cx<T>* in, cx<T>* out, Geo g, int nf, const cx<T>* __restrict__ tw, T scale) {
+  using CG = ColGeo<N, TX>;
+  __shared__ cx<T> lds[N * CG::LD];
+  const int nbx = (g.nxh + TX - 1) / TX;
+  const int xb = blockIdx.x % nbx;
+  const int o = blockIdx.x / nbx;  // fixed z (AXIS 1) or fixed y (AXIS 2)
+  const int col = threadIdx.x % TX;
+  const int bf = threadIdx.x / TX;
+  const int x = xb * TX + col;
+  const bool valid = x < g.nxh;
+  const long long lstride = AXIS == 1 ? (long long)g.P : (long long)g.ny * g.P;
+  const long long base = AXIS == 1 ? (long long)o * g.ny * g.P + x : (long long)o * g.P + x;
+  auto buf = [&](int pos) -> cx<T>& { return lds[pos * CG::LD + col]; };
+  for (int f = 0; f < nf; ++f) {
+    cx<T> a[CG::R0];
+    const long long fb = f * g.fs + base;
+#pragma unroll
+    for (int t = 0; t < CG::R0; ++t) {
+      const int q = bf + t * CG::TL;
+      a[t] = valid ? in[fb + q * lstride] : mk<T>(0, 0);
+    }
+    line_fft<T, N, S>(a, bf, tw, buf);
+    if (valid) {
+#pragma unroll
+      for (int t = 0; t < CG::R0; ++t) {
+        const int q = bf + t * CG::TL;
+        out[fb + q * lstride] = scale * a[t];
+      }
+    }
+  }
+}
+
+// ---- K-E: forward z-FFT of theta, elastic solve, explicit CH, inverse z ----
+template <typename T, typename TE, int N, int TX>
+__global__ void __launch_bounds__((ColGeo<N, TX>::THREADS))
+k_zpass_elastic(cx<T>* __restrict__ th, Geo g, ModelK m, const cx<T>* __restrict__ twz,
+                cx<TE>* __restrict__ FEc, int accumulate) {
+  using CG = ColGeo<N, TX>;
+  __shared__ cx<T> lds[N * CG::LD];
+  const int nbx = (g.nxh + TX - 1) / TX;
+  const int xb = blockIdx.x % nbx;
+  const int y = blockIdx.x / nbx;
+  const int col = threadIdx.x % TX;
+  const int bf = threadIdx.x / TX;
+  const int x = xb * TX + col;
+  const bool valid = x < g.nxh;
+  const long long lstride = (long long)g.ny * g.P;
+  const long long base = (long long)y * g.P + x;
+  auto buf = [&](int pos) -> cx<T>& { return lds[pos * CG::LD + col]; };
+  cx<T> a[3][CG::R0];
+#pragma unroll
+  for (int v = 0; v < 3; ++v) {
+#pragma unroll
+    for (int t = 0; t < CG::R0; ++t) {
+      const int z = bf + t * CG::TL;
+      a[v][t] = valid ? th[v * g.fs + base + z * lstride] : mk<T>(0, 0);
+    }
+    line_fft<T, N, -1>(a[v], bf, twz, buf);
+  }
+  const T kx = (T)(x * g.kfx);
+  const T ky = (T)(mode_of(y, g.ny) * g.kfy);
+#pragma unroll
+  for (int t = 0; t < CG::R0; ++t) {
+    const int z = bf + t * CG::TL;
+    const T kz = (T)(mode_of(z, g.nz) * g.kfz);
+    cx<T> thv[3] = {a[0][t], a[1][t], a[2][t]};
+    cx<T> e[3];
+    const bool k0 = (x == 0) && (y == 0) && (z == 0);
+    if (k0) {
+#pragma unroll
+      for (int v = 0; v < 3; ++v) {
+        cx<T> acc = mk<T>((T)m.hom[v], 0);
+#pragma unroll
+        for (int w = 0; w < 3; ++w) acc = acc + (T)m.B0[v][w] * thv[w];
+        e[v] = acc;
+      }
+    } else {
+      elastic_apply<T>(m, kx, ky, kz, thv, e);
+    }
+    if (valid) {
+      const T k2 = kx * kx + ky * ky + kz * kz;
+      cx<T> Hs = thv[0] + thv[1] + thv[2];
+      cx<T> fe = ((T)m.fEc * k2) * Hs;
+      const long long idx = base + z * lstride;
+      if (accumulate) {
+        cx<TE> old = FEc[idx];
+        FEc[idx] = mk<TE>((TE)(old.re + fe.re), (TE)(old.im + fe.im));
+      } else {
+        FEc[idx] = mk<TE>((TE)fe.re, (TE)fe.im);
+      }
+    }
+    const T s = (T)m.inv_n3;
+#pragma unroll
+    for (int v = 0; v < 3; ++v) a[v][t] = s * e[v];
+  }
+#pragma unroll
+  for (int v = 0; v < 3; ++v) {
+    line_fft<T, N, +1>(a[v], bf, twz, buf);
+    if (valid) {
+#pragma unroll
+      for (int t = 0; t < CG::R0; ++t) {
+        const int z = bf + t * CG::TL;
+        th[v * g.fs + base + z * lstride] = a[v][t];
+      }
+    }
+  }
+}
+
+// ---- K-I: forward z-FFT of the AC driving force, F^E_eta = -L g~ ----------
+template <typename T, typename TE, int N, int TX>
+__global__ void __launch_bounds__((ColGeo<N, TX>::THREADS))
+k_zpass_fwd_ac(const cx<T>* __restrict__ gk, Geo g, ModelK m, const cx<T>* __restrict__ twz,
+               cx<TE>* __restrict__ FE) {
+  using CG = ColGeo<N, TX>;
+  __shared__ cx<T> lds[N * CG::LD];
+  const int nbx = (g.nxh + TX - 1) / TX;
+  const int xb = blockIdx.x % nbx;
+  const int y = blockIdx.x / nbx;
+  const int col = threadIdx.x % TX;
+  const int bf = threadIdx.x / TX;
+  const int x = xb * TX + col;
+  const bool valid = x < g.nxh;
+  const long long lstride = (long long)g.ny * g.P;
+  const long long base = (long long)y * g.P + x;
+  auto buf = [&](int pos) -> cx<T>& { return lds[pos * CG::LD + col]; };
+  const T nl = (T)(-m.L);
+  for (int v = 0; v < 3; ++v) {
+    cx<T> a[CG::R0];
+#pragma unroll
+    for (int t = 0; t < CG::R0; ++t) {
+      const int z = bf + t * CG::TL;
+      a[t] = valid ? gk[v * g.fs + base + z * lstride] : mk<T>(0, 0);
+    }
+    line_fft<T, N, -1>(a, bf, twz, buf);
+    if (valid) {
+#pragma unroll
+      for (int t = 0; t < CG::R0; ++t) {
+        const int z = bf + t * CG::TL;
+        cx<T> r = nl * a[t];
+        FE[(1 + v) * g.fs + base + z * lstride] = mk<TE>((TE)r.re, (TE)r.im);
+      }
+    }
+  }
+}
+
+// ---- row (x-axis) passes ---------------------------------------------------
+template <int M, int RB>
+struct RowGeo {
+  static constexpr int R0 = plan(M).r[0];
+  static constexpr int TL = M / R0;
+  static constexpr int THREADS = RB * TL;
+  static constexpr int LD = M + 2;
+};
+
+// c2r of one half-spectrum row src[0..M] into real pairs a[t] = (x_{2n}, x_{2n+1}),
+// n = bf + t TL.  Unnormalised (full-spectrum sum).
+template <typename T, int M, int RB>
+__device__ inline void row_c2r(const cx<T>* src, bool rvalid, cx<T>* a, int bf, cx<T>* rbuf,
+                               const cx<T>* twN, const cx<T>* twM) {
+  using RG = RowGeo<M, RB>;
+  __syncthreads();
+#pragma unroll
+  for (int t = 0; t < RG::R0; ++t) {
+    const int k = bf + t * RG::TL;
+    rbuf[k] = rvalid ? src[k] : mk<T>(0, 0);
+  }
+  if (bf == 0) rbuf[M] = rvalid ? src[M] : mk<T>(0, 0);
+  __syncthreads();
+#pragma unroll
+  for (int t = 0; t < RG::R0; ++t) {
+    const int k = bf + t * RG::TL;
+    cx<T> xk = rbuf[k];
+    cx<T> xmk = rbuf[M - k];
+    if (k == 0) {
+      xk.im = (T)0;
+      xmk.im = (T)0;
+    }
+    a[t] = c2r_pre(xk, xmk, twN[k]);
+  }
+  line_fft<T, M, +1>(a, bf, twM, [&](int pos) -> cx<T>& { return rbuf[pos]; });
+}
+
+// r2c of real pairs a[t] (n = bf + t TL) into half-spectrum row dst[0..M].
+template <typename T, int M, int RB>
+__device__ inline void row_r2c(cx<T>* a, cx<T>* dst, bool rvalid, int bf, cx<T>* rbuf,
+                               const cx<T>* twN, const cx<T>* twM) {
+  using RG = RowGeo<M, RB>;
+  line_fft<T, M, -1>(a, bf, twM, [&](int pos) -> cx<T>& { return rbuf[pos]; });
+  __syncthreads();
+#pragma unroll
+  for (int t = 0; t < RG::R0; ++t) rbuf[bf + t * RG::TL] = a[t];
+  __syncthreads();
+  if (rvalid) {
+#pragma unroll
+    for (int t = 0; t < RG::R0; ++t) {
+      const int k = bf + t * RG::TL;
+      const cx<T> zk = rbuf[k];
+      const cx<T> zmk = rbuf[k == 0 ? 0 : M - k];
+      dst[k] = r2c_post(zk, zmk, twN[k]);
+    }
+    if (bf == 0) {
+      const cx<T> z0 = rbuf[0];
+      dst[M] = mk<T>(z0.re - z0.im, (T)0);
+    }
+  }
+}
+
+template <typename T>
+__device__ inline T hfun(T e) { return e * e * e * (e * ((T)6 * e - (T)15) + (T)10); }
+template <typename T>
+__device__ inline T dhfun(T e) {
+  const T u = e * ((T)1 - e);
+  return (T)30 * u * u;
+}
+
+// K-C: theta_v = h(eta_v) (rows of the 3 eta fields of `st` -> rows of `th`).
+template <typename T, int M, int RB>
+__global__ void __launch_bounds__((RowGeo<M, RB>::THREADS))
+k_xpass_theta(const cx<T>* __restrict__ st, cx<T>* __restrict__ th, Geo g,
+              const cx<T>* __restrict__ twN, const cx<T>* __restrict__ twM) {
+  using RG = RowGeo<M, RB>;
+  __shared__ cx<T> lds[RB * RG::LD];
+  const int rl = threadIdx.x / RG::TL;
+  const int bf = threadIdx.x % RG::TL;
+  const int row = blockIdx.x * RB + rl;
+  const bool rvalid = row < g.nz * g.ny;
+  cx<T>* rbuf = lds + rl * RG::LD;
+  const long long rb = (long long)(rvalid ? row : 0) * g.P;
+  for (int v = 0; v < 3; ++v) {
+    cx<T> a[RG::R0];
+    row_c2r<T, M, RB>(st + (1 + v) * g.fs + rb, rvalid, a, bf, rbuf, twN, twM);
+#pragma unroll
+    for (int t = 0; t < RG::R0; ++t) a[t] = mk<T>(hfun(a[t].re), hfun(a[t].im));
+    row_r2c<T, M, RB>(a, th + v * g.fs + rb, rvalid, bf, rbuf, twN, twM);
+  }
+}
+
+// K-G: g_v = h'(eta_v) (chi(c) + e_v) + 2 w eta_v (1 - eta_v)(1 - 2 eta_v).
+template <typename T, int M, int RB>
+__global__ void __launch_bounds__((RowGeo<M, RB>::THREADS))
+k_xpass_drive(const cx<T>* __restrict__ st, cx<T>* __restrict__ el, Geo g, ModelK m,
+              const cx<T>* __restrict__ twN, const cx<T>* __restrict__ twM) {
+  using RG = RowGeo<M, RB>;
+  __shared__ cx<T> lds[RB * RG::LD];
+  const int rl = threadIdx.x / RG::TL;
+  const int bf = threadIdx.x % RG::TL;
+  const int row = blockIdx.x * RB + rl;
+  const bool rvalid = row < g.nz * g.ny;
+  cx<T>* rbuf = lds + rl * RG::LD;
+  const long long rb = (long long)(rvalid ? row : 0) * g.P;
+  const T W = (T)m.W, cm = (T)m.cm, cp = (T)m.cp, w2 = (T)(2.0 * m.w);
+  cx<T> chi[RG::R0];
+  {
+    cx<T> a[RG::R0];
+    row_c2r<T, M, RB>(st + rb, rvalid, a, bf, rbuf, twN, twM);
+#pragma unroll
+    for (int t = 0; t < RG::R0; ++t) {
+      const T c0 = a[t].re, c1 = a[t].im;
+      chi[t] = mk<T>(W * ((c0 - cp) * (c0 - cp) - (c0 - cm) * (c0 - cm)),
+                     W * ((c1 - cp) * (c1 - cp) - (c1 - cm) * (c1 - cm)));
+    }
+  }
+  for (int v = 0; v < 3; ++v) {
+    cx<T> et[RG::R0], a[RG::R0];
+    row_c2r<T, M, RB>(st + (1 + v) * g.fs + rb, rvalid, et, bf, rbuf, twN, twM);
+    row_c2r<T, M, RB>(el + v * g.fs + rb, rvalid, a, bf, rbuf, twN, twM);
+#pragma unroll
+    for (int t = 0; t < RG::R0; ++t) {
+      const T e0 = et[t].re, e1 = et[t].im;
+      const T g0 = dhfun(e0) * (chi[t].re + a[t].re) + w2 * e0 * ((T)1 - e0) * ((T)1 - (T)2 * e0);
+      const T g1 = dhfun(e1) * (chi[t].im + a[t].im) + w2 * e1 * ((T)1 - e1) * ((T)1 - (T)2 * e1);
+      a[t] = mk<T>(g0, g1);
+    }
+    row_r2c<T, M, RB>(a, el + v * g.fs + rb, rvalid, bf, rbuf, twN, twM);
+  }
+}
+
+// Standalone row r2c: real rows (length 2M, pitch 2M) -> half-spectrum rows.
+template <typename T, int M, int RB>
+__global__ void __launch_bounds__((RowGeo<M, RB>::THREADS))
+k_xpass_r2c(const T* __restrict__ re, cx<T>* __restrict__ out, Geo g, int nf,
+            const cx<T>* __restrict__ twN, const cx<T>* __restrict__ twM) {
+  using RG = RowGeo<M, RB>;
+  __shared__ cx<T> lds[RB * RG::LD];
+  const int rl = threadIdx.x / RG::TL;
+  const int bf = threadIdx.x % RG::TL;
+  const int row = blockIdx.x * RB + rl;
+  const int nrows = g.nz * g.ny;
+  const bool rvalid = row < nrows;
+  cx<T>* rbuf = lds + rl * RG::LD;
+  const long long rr = rvalid ? row : 0;
+  for (int f = 0; f < nf; ++f) {
+    const cx<T>* src = reinterpret_cast<const cx<T>*>(re + ((long long)f * nrows + rr) * (2 * M));
+    cx<T> a[RG::R0];
+#pragma unroll
+    for (int t = 0; t < RG::R0; ++t) a[t] = rvalid ? src[bf + t * RG::TL] : mk<T>(0, 0);
+    row_r2c<T, M, RB>(a, out + f * g.fs + rr * g.P, rvalid, bf, rbuf, twN, twM);
+  }
+}
+
+// Standalone row c2r: half-spectrum rows -> real rows, times `scale`.
+template <typename T, int M, int RB>
+__global__ void __launch_bounds__((RowGeo<M, RB>::THREADS))
+k_xpass_c2r(const cx<T>* __restrict__ in, T* __restrict__ re, Geo g, int nf, T scale,
+            const cx<T>* __restrict__ twN, const cx<T>* __restrict__ twM) {
+  using RG = RowGeo<M, RB>;
+  __shared__ cx<T> lds[RB * RG::LD];
+  const int rl = threadIdx.x / RG::TL;
+  const int bf = threadIdx.x % RG::TL;
+  const int row = blockIdx.x * RB + rl;
+  const int nrows = g.nz * g.ny;
+  const bool rvalid = row < nrows;
+  cx<T>* rbuf = lds + rl * RG::LD;
+  const long long rr = rvalid ? row : 0;
+  for (int f = 0; f < nf; ++f) {
+    cx<T> a[RG::R0];
+    row_c2r<T, M, RB>(in + f * g.fs + rr * g.P, rvalid, a, bf, rbuf, twN, twM);
+    if (rvalid) {
+      cx<T>* dst = reinterpret_cast<cx<T>*>(re + ((long long)f * nrows + rr) * (2 * M));
+#pragma unroll
+      for (int t = 0; t < RG::R0; ++t) dst[bf + t * RG::TL] = scale * a[t];
+    }
+  }
+}
+
+// ---- reductions ------------------------------------------------------------
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Block sum (blockDim.x multiple of 64, <= 1024); result valid in thread 0.
+__device__ inline double block_sum(double v, double* sh) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) sh[wid] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0) {
+    const int nw = (blockDim.x + 63) >> 6;
+    for (int i = 0; i < nw; ++i) r += sh[i];
+  }
+  __syncthreads();
+  return r;
+}
+
+// ---- finalize: update, embedded error, WRMS partial sums ------------------
+template <typename TE>
+struct FinArgs {
+  const cx<double>* y;
+  cx<double>* ynew;
+  const cx<TE>* FE[6];
+  const cx<double>* FI[6];
+  double bE[6], bI[6];   // update weights (times dt)
+  double dE[6], dI[6];   // error weights (b - b~) times dt
+  int s;
+  int want_err;
+  double rtol, atol, sc;  // sc = 1/sqrt(N^3)
+  double* partial;        // [2 * gridDim.x]: sum of squares, non-finite count
+};
+
+template <typename TE>
+__global__ void __launch_bounds__(256) k_finalize(FinArgs<TE> fa, Geo g) {
+  __shared__ double sh[16];
+  const long long nrow = (long long)g.nz * g.ny;
+  const long long total = 4 * nrow * g.nxh;
+  double acc = 0.0, bad = 0.0;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
+       i += (long long)gridDim.x * blockDim.x) {
+    const int x = (int)(i % g.nxh);
+    const long long fr = i / g.nxh;  // f * nrow + row
+    const long long idx = fr * g.P + x;
+    const cx<double> y0 = fa.y[idx];
+    cx<double> inc = mk(0.0, 0.0), err = mk(0.0, 0.0);
+    for (int j = 0; j < fa.s; ++j) {
+      const bool hasI = fa.bI[j] != 0.0 || (fa.want_err && fa.dI[j] != 0.0);
+      const bool hasE = fa.bE[j] != 0.0 || (fa.want_err && fa.dE[j] != 0.0);
+      cx<double> fi = mk(0.0, 0.0), fe = mk(0.0, 0.0);
+      if (hasI) fi = fa.FI[j][idx];
+      if (hasE) fe = to_d(fa.FE[j][idx]);
+      if (fa.bI[j] != 0.0) inc = inc + fa.bI[j] * fi;
+      if (fa.bE[j] != 0.0) inc = inc + fa.bE[j] * fe;
+      if (fa.want_err) err = err + (fa.dI[j] * fi + fa.dE[j] * fe);
+    }
+    const cx<double> yn = y0 + inc;
+    fa.ynew[idx] = yn;
+    if (!isfinite(yn.re) || !isfinite(yn.im)) bad += 1.0;
+    if (fa.want_err) {
+      const double mult = (x == 0 || 2 * x == g.nx) ? 1.0 : 2.0;
+      const double ay = sqrt(y0.re * y0.re + y0.im * y0.im) * fa.sc;
+      const double wgt = 1.0 / (fa.rtol * ay + fa.atol);
+      const double e2 = (err.re * err.re + err.im * err.im) * fa.sc * fa.sc;
+      acc += mult * e2 * wgt * wgt;
+    }
+  }
+  const double s0 = block_sum(acc, sh);
+  const double s1 = block_sum(bad, sh);
+  if (threadIdx.x == 0) {
+    fa.partial[2 * blockIdx.x] = s0;
+    fa.partial[2 * blockIdx.x + 1] = s1;
+  }
+}
+
+// Sums n (value, flag) partial pairs in a fixed order into out[0], out[1].
+__global__ void __launch_bounds__(256) k_reduce_pairs(const double* partial, int n, double* out) {
+  __shared__ double sh[16];
+  double a = 0.0, b = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    a += partial[2 * i];
+    b += partial[2 * i + 1];
+  }
+  a = block_sum(a, sh);
+  b = block_sum(b, sh);
+  if (threadIdx.x == 0) {
+    out[0] = a;
+    out[1] = b;
+  }
+}
+
+// Volume fraction partial sums over real fields [4][N] (c, eta_1..3).
+__global__ void __launch_bounds__(256) k_vf_partial(const double* u, long long npts, double* partial) {
+  __shared__ double sh[16];
+  double hs = 0.0, cnt = 0.0;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < npts;
+       i += (long long)gridDim.x * blockDim.x) {
+    const double e1 = u[npts + i], e2 = u[2 * npts + i], e3 = u[3 * npts + i];
+    hs += hfun(e1) + hfun(e2) + hfun(e3);
+    const double mx = fmax(e1, fmax(e2, e3));
+    cnt += mx > 0.5 ? 1.0 : 0.0;
+  }
+  hs = block_sum(hs, sh);
+  cnt = block_sum(cnt, sh);
+  if (threadIdx.x == 0) {
+    partial[2 * blockIdx.x] = hs;
+    partial[2 * blockIdx.x + 1] = cnt;
+  }
+}
+
+// Element-wise copy with precision conversion over valid k-space entries.
+template <typename TA, typename TB>
+__global__ void __launch_bounds__(256) k_convert(const cx<TA>* a, cx<TB>* b, Geo g, int nf) {
+  const long long total = (long long)nf * g.fs;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
+       i += (long long)gridDim.x * blockDim.x) {
+    const cx<TA> v = a[i];
+    b[i] = mk<TB>((TB)v.re, (TB)v.im);
+  }
+}
+
+}  // namespace pf

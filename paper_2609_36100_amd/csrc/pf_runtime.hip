@@ -1,0 +1,962 @@
+// libpf host runtime: context, workspace, stage pipeline, step control, C ABI.
+//
+// Time integration follows Methods, "Time integration": the ImEx-ARK stage
+// and update formulas (Eq. ARK_method), the embedded solution
+// (Eq. ARK_embedding), the WRMS test (Eqs. wrms_norm, wrms_weights) and the
+// reject / recompute / accept cycle.  The implicit stage solve is the per-mode
+// division the paper wraps as a custom linear solver; here it is fused into
+// the first kernel of every stage.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <type_traits>
+#include <utility>
+#include <vector>
+
+#include "../../include/pf.h"
+#include "pf_kernels.hpp"
+
+using namespace pf;
+
+// ---- supported line lengths --------------------------------------------
+// Column passes (y, z) take N; row passes (x) take M = nx / 2.
+#define PF_COL_SIZES(X) X(8) X(16) X(24) X(32) X(40) X(48) X(64) X(80) X(96) X(128) X(160) X(192) X(256) X(320) X(384) X(512)
+#define PF_ROW_SIZES(X) X(4) X(8) X(12) X(16) X(20) X(24) X(32) X(40) X(48) X(64) X(80) X(96) X(128) X(160) X(192) X(256)
+
+template <class F>
+static bool col_dispatch(int n, F&& f) {
+  switch (n) {
+#define PF_CASE(N)                          \
+  case N:                                   \
+    f(std::integral_constant<int, N>{});    \
+    return true;
+    PF_COL_SIZES(PF_CASE)
+#undef PF_CASE
+    default:
+      return false;
+  }
+}
+
+template <class F>
+static bool row_dispatch(int m, F&& f) {
+  switch (m) {
+#define PF_CASE(N)                          \
+  case N:                                   \
+    f(std::integral_constant<int, N>{});    \
+    return true;
+    PF_ROW_SIZES(PF_CASE)
+#undef PF_CASE
+    default:
+      return false;
+  }
+}
+
+static bool col_supported(int n) {
+  return col_dispatch(n, [](auto) {});
+}
+static bool row_supported(int m) {
+  return row_dispatch(m, [](auto) {});
+}
+
+// Columns per column-pass work-group: 128 contiguous bytes per row segment.
+template <typename T>
+constexpr int tx_of() { return sizeof(T) == 8 ? 8 : 16; }
+// Rows per row-pass work-group: about 256 threads.
+constexpr int rb_of(int m) { return line_threads(m) >= 256 ? 1 : 256 / line_threads(m); }
+
+// ---- ImEx-ARK tables ---------------------------------------------------------
+struct ArkTable {
+  int s;
+  int order, emb_order;
+  int has_emb;
+  double AE[6][6], AI[6][6], bE[6], bI[6], bt[6];
+};
+
+static ArkTable table_imex_euler() {
+  ArkTable t;
+  std::memset(&t, 0, sizeof(t));
+  t.s = 2;
+  t.order = 1;
+  t.AE[1][0] = 1.0;
+  t.AI[1][1] = 1.0;
+  t.bE[0] = 1.0;
+  t.bI[1] = 1.0;
+  return t;
+}
+
+// ARK4(3)6L[2]SA (Kennedy & Carpenter 2003): published rational coefficients.
+static ArkTable table_ark436l() {
+  ArkTable t;
+  std::memset(&t, 0, sizeof(t));
+  t.s = 6;
+  t.order = 4;
+  t.emb_order = 3;
+  t.has_emb = 1;
+  double(*E)[6] = t.AE;
+  E[1][0] = 1.0 / 2.0;
+  E[2][0] = 13861.0 / 62500.0;
+  E[2][1] = 6889.0 / 62500.0;
+  E[3][0] = -116923316275.0 / 2393684061468.0;
+  E[3][1] = -2731218467317.0 / 15368042101831.0;
+  E[3][2] = 9408046702089.0 / 11113171139209.0;
+  E[4][0] = -451086348788.0 / 2902428689909.0;
+  E[4][1] = -2682348792572.0 / 7519795681897.0;
+  E[4][2] = 12662868775082.0 / 11960479115383.0;
+  E[4][3] = 3355817975965.0 / 11060851509271.0;
+  E[5][0] = 647845179188.0 / 3216320057751.0;
+  E[5][1] = 73281519250.0 / 8382639484533.0;
+  E[5][2] = 552539513391.0 / 3454668386233.0;
+  E[5][3] = 3354512671639.0 / 8306763924573.0;
+  E[5][4] = 4040.0 / 17871.0;
+  const double b[6] = {82889.0 / 524892.0, 0.0, 15625.0 / 83664.0, 69875.0 / 102672.0,
+                       -2260.0 / 8211.0, 1.0 / 4.0};
+  const double bt[6] = {4586570599.0 / 29645900160.0, 0.0, 178811875.0 / 945068544.0,
+                        814220225.0 / 1159782912.0, -3700637.0 / 11593932.0, 61727.0 / 225920.0};
+  double(*I)[6] = t.AI;
+  const double g = 1.0 / 4.0;
+  I[1][0] = g;
+  I[1][1] = g;
+  I[2][0] = 8611.0 / 62500.0;
+  I[2][1] = -1743.0 / 31250.0;
+  I[2][2] = g;
+  I[3][0] = 5012029.0 / 34652500.0;
+  I[3][1] = -654441.0 / 2922500.0;
+  I[3][2] = 174375.0 / 388108.0;
+  I[3][3] = g;
+  I[4][0] = 15267082809.0 / 155376265600.0;
+  I[4][1] = -71443401.0 / 120774400.0;
+  I[4][2] = 730878875.0 / 902184768.0;
+  I[4][3] = 2285395.0 / 8070912.0;
+  I[4][4] = g;
+  for (int j = 0; j < 6; ++j) {
+    I[5][j] = b[j];
+    t.bE[j] = b[j];
+    t.bI[j] = b[j];
+    t.bt[j] = bt[j];
+  }
+  return t;
+}
+
+static bool fe_needed(const ArkTable& t, int i) {
+  if (t.bE[i] != 0.0 || (t.has_emb && t.bt[i] != 0.0)) return true;
+  for (int k = i + 1; k < t.s; ++k)
+    if (t.AE[k][i] != 0.0) return true;
+  return false;
+}
+static bool fi_needed(const ArkTable& t, int i) {
+  if (t.bI[i] != 0.0 || (t.has_emb && t.bI[i] - t.bt[i] != 0.0)) return true;
+  for (int k = i + 1; k < t.s; ++k)
+    if (t.AI[k][i] != 0.0) return true;
+  return false;
+}
+
+// ---- context -----------------------------------------------------------------
+struct pf_ctx {
+  pf_params p;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  Geo g;
+  ModelK mk;
+  ArkTable tab;
+  bool fe_need[6], fi_need[6];
+  int mixed = 0;
+
+  cx<double>* y = nullptr;
+  cx<double>* ynew = nullptr;
+  cx<double>* FI[6] = {nullptr};
+  void* FE[6] = {nullptr};  // cx<double> (FP64) or cx<float> (mixed)
+  void* scratch = nullptr;  // T1 (4 fields) | T3 (3 fields) of the FFT precision
+  size_t scratch_bytes = 0;
+  double* partial = nullptr;
+  double* red = nullptr;
+  double* host_red = nullptr;  // pinned
+  int nblk_red = 1024;
+
+  // twiddle tables: 0 = z (N_z), 1 = y (N_y), 2 = x half length (M), 3 = x real length (N_x)
+  cx<double>* tw64[4] = {nullptr};
+  cx<float>* tw32[4] = {nullptr};
+
+  // per-kernel-class HIP-event timing (off by default)
+  bool prof_on = false;
+  std::vector<hipEvent_t> prof_ev;
+  size_t prof_used = 0;
+  std::vector<std::pair<int, double>> prof_pending;  // (class, algorithmic bytes)
+  double prof_ms[16] = {0}, prof_bytes[16] = {0};
+  int64_t prof_n[16] = {0};
+
+  int64_t ws_bytes = 0;
+  double t = 0.0;
+  double dt_next = 0.0;
+  bool have_state = false;
+  pf_stats st;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+};
+
+#define PF_HIP(call)                                   \
+  do {                                                 \
+    hipError_t e_ = (call);                            \
+    if (e_ != hipSuccess) return PF_ERR_HIP;           \
+  } while (0)
+
+static pf_status dalloc(pf_ctx* c, void** p, size_t bytes) {
+  if (hipMalloc(p, bytes) != hipSuccess) {
+    *p = nullptr;
+    return PF_ERR_OOM;
+  }
+  c->ws_bytes += (int64_t)bytes;
+  return PF_OK;
+}
+
+template <typename T>
+static void make_twiddles(int n, cx<T>* host) {
+  const long double pi = 3.141592653589793238462643383279502884L;
+  for (int j = 0; j < n; ++j) {
+    const long double a = 2.0L * pi * (long double)j / (long double)n;
+    host[j].re = (T)cosl(a);
+    host[j].im = (T)(-sinl(a));
+  }
+}
+
+static pf_status upload_twiddles(pf_ctx* c, int slot, int n) {
+  cx<double>* h64 = new (std::nothrow) cx<double>[n];
+  cx<float>* h32 = new (std::nothrow) cx<float>[n];
+  if (!h64 || !h32) {
+    delete[] h64;
+    delete[] h32;
+    return PF_ERR_OOM;
+  }
+  make_twiddles<double>(n, h64);
+  make_twiddles<float>(n, h32);
+  pf_status s = dalloc(c, (void**)&c->tw64[slot], sizeof(cx<double>) * n);
+  if (s == PF_OK) s = dalloc(c, (void**)&c->tw32[slot], sizeof(cx<float>) * n);
+  if (s == PF_OK && hipMemcpy(c->tw64[slot], h64, sizeof(cx<double>) * n, hipMemcpyHostToDevice) != hipSuccess)
+    s = PF_ERR_HIP;
+  if (s == PF_OK && hipMemcpy(c->tw32[slot], h32, sizeof(cx<float>) * n, hipMemcpyHostToDevice) != hipSuccess)
+    s = PF_ERR_HIP;
+  delete[] h64;
+  delete[] h32;
+  return s;
+}
+
+template <typename T>
+static const cx<T>* tw(const pf_ctx* c, int slot) {
+  if constexpr (sizeof(T) == 8)
+    return c->tw64[slot];
+  else
+    return c->tw32[slot];
+}
+
+static void setup_model(pf_ctx* c) {
+  const pf_params& p = c->p;
+  ModelK& m = c->mk;
+  std::memset(&m, 0, sizeof(m));
+  m.M = p.M;
+  m.L = p.L;
+  m.kc = p.kappa_c;
+  m.ke = p.kappa_eta;
+  m.ac = p.implicit_bulk_c ? 2.0 * p.W : 0.0;
+  m.W = p.W;
+  m.w = p.w;
+  m.cm = p.c_m;
+  m.cp = p.c_p;
+  m.fEc = 2.0 * p.W * p.M * (p.c_p - p.c_m);
+  m.fEa = (2.0 * p.W - m.ac) * p.M;
+  m.C11 = p.C11;
+  m.C12 = p.C12;
+  m.C44 = p.C44;
+  const double n3 = (double)p.nx * p.ny * p.nz;
+  m.inv_n3 = 1.0 / n3;
+  for (int v = 0; v < 3; ++v) {
+    const double* e = p.eps_star[v];
+    const double tr = e[0] + e[1] + e[2];
+    for (int i = 0; i < 3; ++i) m.S[v][i] = p.C12 * tr + (p.C11 - p.C12) * e[i];
+  }
+  for (int v = 0; v < 3; ++v)
+    for (int w = 0; w < 3; ++w) {
+      double s = 0.0;
+      for (int i = 0; i < 3; ++i) s += p.eps_star[v][i] * m.S[w][i];
+      m.E[v][w] = s;
+      m.B0[v][w] = p.mean_strain_mode == 0 ? s : 0.0;
+    }
+  for (int v = 0; v < 3; ++v) {
+    double s = 0.0;
+    if (p.mean_strain_mode == 0)
+      for (int i = 0; i < 3; ++i) s += p.eps_bar[i] * m.S[v][i];
+    m.hom[v] = -n3 * s;
+  }
+}
+
+// ---- launchers ----------------------------------------------------------------
+template <typename T, typename TE>
+static bool launch_stage_invz(pf_ctx* c, const StageArgs<TE>& sa, cx<T>* out, int do_fft) {
+  const Geo& g = c->g;
+  constexpr int TX = tx_of<T>();
+  return col_dispatch(g.nz, [&](auto NC) {
+    constexpr int N = decltype(NC)::value;
+    const int nbx = (g.nxh + TX - 1) / TX;
+    k_stage_invz<T, TE, N, TX><<<dim3(nbx * g.ny), dim3(ColGeo<N, TX>::THREADS), 0, c->stream>>>(
+        sa, g, c->mk, tw<T>(c, 0), out, do_fft);
+  });
+}
+
+template <typename T, int S, int AXIS>
+static bool launch_colfft(pf_ctx* c, const cx<T>* in, cx<T>* out, int nf, T scale) {
+  const Geo& g = c->g;
+  constexpr int TX = tx_of<T>();
+  const int n = AXIS == 1 ? g.ny : g.nz;
+  const int other = AXIS == 1 ? g.nz : g.ny;
+  return col_dispatch(n, [&](auto NC) {
+    constexpr int N = decltype(NC)::value;
+    const int nbx = (g.nxh + TX - 1) / TX;
+    k_colfft<T, N, TX, S, AXIS><<<dim3(nbx * other), dim3(ColGeo<N, TX>::THREADS), 0, c->stream>>>(
+        in, out, g, nf, tw<T>(c, AXIS == 1 ? 1 : 0), scale);
+  });
+}
+
+template <typename T, typename TE>
+static bool launch_zpass_elastic(pf_ctx* c, cx<T>* th, cx<TE>* FEc, int accumulate) {
+  const Geo& g = c->g;
+  constexpr int TX = tx_of<T>();
+  return col_dispatch(g.nz, [&](auto NC) {
+    constexpr int N = decltype(NC)::value;
+    const int nbx = (g.nxh + TX - 1) / TX;
+    k_zpass_elastic<T, TE, N, TX><<<dim3(nbx * g.ny), dim3(ColGeo<N, TX>::THREADS), 0, c->stream>>>(
+        th, g, c->mk, tw<T>(c, 0), FEc, accumulate);
+  });
+}
+
+template <typename T, typename TE>
+static bool launch_zpass_fwd_ac(pf_ctx* c, const cx<T>* gk, cx<TE>* FE) {
+  const Geo& g = c->g;
+  constexpr int TX = tx_of<T>();
+  return col_dispatch(g.nz, [&](auto NC) {
+    constexpr int N = decltype(NC)::value;
+    const int nbx = (g.nxh + TX - 1) / TX;
+    k_zpass_fwd_ac<T, TE, N, TX><<<dim3(nbx * g.ny), dim3(ColGeo<N, TX>::THREADS), 0, c->stream>>>(
+        gk, g, c->mk, tw<T>(c, 0), FE);
+  });
+}
+
+template <typename T>
+static bool launch_xpass_theta(pf_ctx* c, const cx<T>* st, cx<T>* th) {
+  const Geo& g = c->g;
+  return row_dispatch(g.nx / 2, [&](auto MC) {
+    constexpr int M = decltype(MC)::value;
+    constexpr int RB = rb_of(M);
+    const int nrows = g.nz * g.ny;
+    k_xpass_theta<T, M, RB><<<dim3((nrows + RB - 1) / RB), dim3(RowGeo<M, RB>::THREADS), 0, c->stream>>>(
+        st, th, g, tw<T>(c, 3), tw<T>(c, 2));
+  });
+}
+
+template <typename T>
+static bool launch_xpass_drive(pf_ctx* c, const cx<T>* st, cx<T>* el) {
+  const Geo& g = c->g;
+  return row_dispatch(g.nx / 2, [&](auto MC) {
+    constexpr int M = decltype(MC)::value;
+    constexpr int RB = rb_of(M);
+    const int nrows = g.nz * g.ny;
+    k_xpass_drive<T, M, RB><<<dim3((nrows + RB - 1) / RB), dim3(RowGeo<M, RB>::THREADS), 0, c->stream>>>(
+        st, el, g, c->mk, tw<T>(c, 3), tw<T>(c, 2));
+  });
+}
+
+static bool launch_xpass_r2c(pf_ctx* c, const double* re, cx<double>* out, int nf) {
+  const Geo& g = c->g;
+  return row_dispatch(g.nx / 2, [&](auto MC) {
+    constexpr int M = decltype(MC)::value;
+    constexpr int RB = rb_of(M);
+    const int nrows = g.nz * g.ny;
+    k_xpass_r2c<double, M, RB><<<dim3((nrows + RB - 1) / RB), dim3(RowGeo<M, RB>::THREADS), 0, c->stream>>>(
+        re, out, g, nf, tw<double>(c, 3), tw<double>(c, 2));
+  });
+}
+
+static bool launch_xpass_c2r(pf_ctx* c, const cx<double>* in, double* re, int nf, double scale) {
+  const Geo& g = c->g;
+  return row_dispatch(g.nx / 2, [&](auto MC) {
+    constexpr int M = decltype(MC)::value;
+    constexpr int RB = rb_of(M);
+    const int nrows = g.nz * g.ny;
+    k_xpass_c2r<double, M, RB><<<dim3((nrows + RB - 1) / RB), dim3(RowGeo<M, RB>::THREADS), 0, c->stream>>>(
+        in, re, g, nf, scale, tw<double>(c, 3), tw<double>(c, 2));
+  });
+}
+
+// ---- per-kernel-class timing --------------------------------------------------
+enum KClass {
+  KC_STAGE = 0, KC_YFFT, KC_THETA, KC_ELASTIC, KC_DRIVE, KC_ZFWD_AC, KC_FINAL,
+  KC_XR2C, KC_XC2R, KC_ZFFT, KC_COUNT
+};
+static const char* const kc_names[KC_COUNT] = {
+    "stage_invz", "ypass", "xpass_theta", "zpass_elastic", "xpass_drive",
+    "zpass_fwd_ac", "finalize", "xpass_r2c", "xpass_c2r", "zpass"};
+
+static void prof_begin(pf_ctx* c) {
+  if (!c->prof_on) return;
+  if (c->prof_used + 2 > c->prof_ev.size()) {
+    for (int i = 0; i < 64; ++i) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return;
+      c->prof_ev.push_back(e);
+    }
+  }
+  hipEventRecord(c->prof_ev[c->prof_used], c->stream);
+}
+
+static void prof_end(pf_ctx* c, int cls, double bytes) {
+  if (!c->prof_on || c->prof_used + 2 > c->prof_ev.size()) return;
+  hipEventRecord(c->prof_ev[c->prof_used + 1], c->stream);
+  c->prof_used += 2;
+  c->prof_pending.push_back(std::make_pair(cls, bytes));
+}
+
+// Call after the stream has been synchronised.
+static void prof_resolve(pf_ctx* c) {
+  if (!c->prof_on) return;
+  for (size_t i = 0; i < c->prof_pending.size(); ++i) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, c->prof_ev[2 * i], c->prof_ev[2 * i + 1]) == hipSuccess) {
+      const int k = c->prof_pending[i].first;
+      c->prof_ms[k] += ms;
+      c->prof_n[k] += 1;
+      c->prof_bytes[k] += c->prof_pending[i].second;
+    }
+  }
+  c->prof_pending.clear();
+  c->prof_used = 0;
+}
+
+// ---- one stage: combine / implicit solve, then the explicit RHS chain ---------
+template <typename T, typename TE>
+static pf_status run_stage(pf_ctx* c, const StageArgs<TE>& sa, bool need_rhs, cx<TE>* FE_out) {
+  cx<T>* T1 = (cx<T>*)c->scratch;
+  cx<T>* T3 = T1 + 4 * c->g.fs;
+  // algorithmic bytes: one valid half-spectrum field in T, TE and FP64
+  const double nv = (double)c->g.nz * c->g.ny * c->g.nxh;
+  const double fT = nv * sizeof(cx<T>), fE = nv * sizeof(cx<TE>), f64 = nv * sizeof(cx<double>);
+  double b_stage = 4 * f64;  // state read
+  for (int j = 0; j < sa.nprev; ++j)
+    b_stage += 4 * ((sa.cE[j] != 0.0 ? fE : 0.0) + (sa.cI[j] != 0.0 ? f64 : 0.0));
+  b_stage += (sa.FI_out ? 4 * f64 : 0.0) + (sa.FEc_out ? fE : 0.0) + (need_rhs ? 4 * fT : 0.0);
+  prof_begin(c);
+  if (!launch_stage_invz<T, TE>(c, sa, T1, need_rhs ? 1 : 0)) return PF_ERR_UNSUPPORTED_SIZE;
+  prof_end(c, KC_STAGE, b_stage);
+  if (need_rhs) {
+    const int acc = (sa.FEc_out != nullptr) ? 1 : 0;
+    bool ok = true;
+    prof_begin(c);
+    ok = ok && launch_colfft<T, +1, 1>(c, T1, T1, 4, (T)1);
+    prof_end(c, KC_YFFT, 8 * fT);
+    prof_begin(c);
+    ok = ok && launch_xpass_theta<T>(c, T1, T3);
+    prof_end(c, KC_THETA, 6 * fT);
+    prof_begin(c);
+    ok = ok && launch_colfft<T, -1, 1>(c, T3, T3, 3, (T)1);
+    prof_end(c, KC_YFFT, 6 * fT);
+    prof_begin(c);
+    ok = ok && launch_zpass_elastic<T, TE>(c, T3, FE_out, acc);
+    prof_end(c, KC_ELASTIC, 6 * fT + (acc ? 2 : 1) * fE);
+    prof_begin(c);
+    ok = ok && launch_colfft<T, +1, 1>(c, T3, T3, 3, (T)1);
+    prof_end(c, KC_YFFT, 6 * fT);
+    prof_begin(c);
+    ok = ok && launch_xpass_drive<T>(c, T1, T3);
+    prof_end(c, KC_DRIVE, 10 * fT);
+    prof_begin(c);
+    ok = ok && launch_colfft<T, -1, 1>(c, T3, T3, 3, (T)1);
+    prof_end(c, KC_YFFT, 6 * fT);
+    prof_begin(c);
+    ok = ok && launch_zpass_fwd_ac<T, TE>(c, T3, FE_out);
+    prof_end(c, KC_ZFWD_AC, 3 * fT + 3 * fE);
+    if (!ok) return PF_ERR_UNSUPPORTED_SIZE;
+  }
+  if (hipGetLastError() != hipSuccess) return PF_ERR_HIP;
+  return PF_OK;
+}
+
+template <typename T, typename TE>
+static pf_status stages_and_finalize(pf_ctx* c, double dt, int* n_rhs) {
+  const ArkTable& tb = c->tab;
+  *n_rhs = 0;
+  for (int i = 0; i < tb.s; ++i) {
+    StageArgs<TE> sa;
+    std::memset(&sa, 0, sizeof(sa));
+    sa.y = c->y;
+    for (int j = 0; j < i; ++j) {
+      sa.FE[j] = (const cx<TE>*)c->FE[j];
+      sa.FI[j] = c->FI[j];
+      sa.cE[j] = (c->fe_need[j] ? dt * tb.AE[i][j] : 0.0);
+      sa.cI[j] = (c->fi_need[j] ? dt * tb.AI[i][j] : 0.0);
+    }
+    sa.nprev = i;
+    sa.gdt = dt * tb.AI[i][i];
+    sa.FI_out = c->fi_need[i] ? c->FI[i] : nullptr;
+    const bool need_rhs = c->fe_need[i];
+    sa.FEc_out = (need_rhs && c->mk.fEa != 0.0) ? (cx<TE>*)c->FE[i] : nullptr;
+    pf_status s = run_stage<T, TE>(c, sa, need_rhs, (cx<TE>*)c->FE[i]);
+    if (s != PF_OK) return s;
+    if (need_rhs) ++*n_rhs;
+  }
+  FinArgs<TE> fa;
+  std::memset(&fa, 0, sizeof(fa));
+  fa.y = c->y;
+  fa.ynew = c->ynew;
+  for (int j = 0; j < tb.s; ++j) {
+    fa.FE[j] = (const cx<TE>*)c->FE[j];
+    fa.FI[j] = c->FI[j];
+    fa.bE[j] = c->fe_need[j] ? dt * tb.bE[j] : 0.0;
+    fa.bI[j] = c->fi_need[j] ? dt * tb.bI[j] : 0.0;
+    fa.dE[j] = (tb.has_emb && c->fe_need[j]) ? dt * (tb.bE[j] - tb.bt[j]) : 0.0;
+    fa.dI[j] = (tb.has_emb && c->fi_need[j]) ? dt * (tb.bI[j] - tb.bt[j]) : 0.0;
+  }
+  fa.s = tb.s;
+  fa.want_err = tb.has_emb;
+  fa.rtol = c->p.rtol;
+  fa.atol = c->p.atol;
+  fa.sc = 1.0 / std::sqrt((double)c->g.nx * c->g.ny * c->g.nz);
+  fa.partial = c->partial;
+  double b_fin = 8.0 * 4 * c->g.nz * (double)c->g.ny * c->g.nxh * 2;  // y read + ynew write (FP64)
+  for (int j = 0; j < tb.s; ++j) {
+    const double nv = 4.0 * c->g.nz * (double)c->g.ny * c->g.nxh;
+    if (fa.bI[j] != 0.0 || fa.dI[j] != 0.0) b_fin += nv * sizeof(cx<double>);
+    if (fa.bE[j] != 0.0 || fa.dE[j] != 0.0) b_fin += nv * sizeof(cx<TE>);
+  }
+  prof_begin(c);
+  k_finalize<TE><<<dim3(c->nblk_red), dim3(256), 0, c->stream>>>(fa, c->g);
+  k_reduce_pairs<<<dim3(1), dim3(256), 0, c->stream>>>(c->partial, c->nblk_red, c->red);
+  prof_end(c, KC_FINAL, b_fin);
+  if (hipGetLastError() != hipSuccess) return PF_ERR_HIP;
+  return PF_OK;
+}
+
+static double controller(double dt, double err, int q, bool after_reject) {
+  if (!std::isfinite(err)) return 0.25 * dt;
+  double fac;
+  if (err == 0.0)
+    fac = 5.0;
+  else
+    fac = std::min(5.0, std::max(0.2, 0.9 * std::pow(err, -1.0 / (q + 1))));
+  if (after_reject) fac = std::min(1.0, fac);
+  return dt * fac;
+}
+
+
+// ---- C ABI ---------------------------------------------------------------------
+extern "C" {
+
+const char* pf_status_string(pf_status s) {
+  switch (s) {
+    case PF_OK: return "PF_OK";
+    case PF_ERR_ARG: return "PF_ERR_ARG";
+    case PF_ERR_OOM: return "PF_ERR_OOM";
+    case PF_ERR_HIP: return "PF_ERR_HIP";
+    case PF_ERR_UNSUPPORTED_SIZE: return "PF_ERR_UNSUPPORTED_SIZE";
+    case PF_ERR_STEP_FAIL: return "PF_ERR_STEP_FAIL";
+    case PF_ERR_NONFINITE: return "PF_ERR_NONFINITE";
+    case PF_ERR_STATE: return "PF_ERR_STATE";
+  }
+  return "PF_UNKNOWN_STATUS";
+}
+
+pf_status pf_default_params(pf_params* p) {
+  if (!p) return PF_ERR_ARG;
+  std::memset(p, 0, sizeof(*p));
+  p->nx = p->ny = p->nz = 32;
+  p->dx = 1.0;
+  p->W = p->w = p->kappa_c = p->kappa_eta = p->M = p->L = 1.0;
+  p->c_m = 0.02;
+  p->c_p = 0.25;
+  p->C11 = 250.0;
+  p->C12 = 150.0;
+  p->C44 = 120.0;
+  for (int v = 0; v < 3; ++v)
+    for (int i = 0; i < 3; ++i) p->eps_star[v][i] = (v == i) ? 0.0286 : 0.0067;
+  p->mean_strain_mode = 0;
+  p->implicit_bulk_c = 1;
+  p->precision = PF_FP64;
+  p->method = PF_ARK436L;
+  p->adaptive = 0;
+  p->dt0 = 1e-2;
+  p->rtol = 1e-6;
+  p->atol = 1e-9;
+  p->dt_min = 0.0;
+  p->dt_max = 1e300;
+  p->max_rejects = 10;
+  return PF_OK;
+}
+
+int32_t pf_size_supported(int32_t n) {
+  if (n < 8 || n > 512 || n % 8 != 0) return 0;
+  return (col_supported(n) && row_supported(n / 2)) ? 1 : 0;
+}
+
+void pf_finalize(pf_ctx* c) {
+  if (!c) return;
+  hipFree(c->y);
+  hipFree(c->ynew);
+  for (int i = 0; i < 6; ++i) {
+    hipFree(c->FI[i]);
+    hipFree(c->FE[i]);
+  }
+  hipFree(c->scratch);
+  hipFree(c->partial);
+  hipFree(c->red);
+  if (c->host_red) hipHostFree(c->host_red);
+  for (int s = 0; s < 4; ++s) {
+    hipFree(c->tw64[s]);
+    hipFree(c->tw32[s]);
+  }
+  if (c->ev0) hipEventDestroy(c->ev0);
+  if (c->ev1) hipEventDestroy(c->ev1);
+  delete c;
+}
+
+pf_status pf_init(const pf_params* p, void* stream, pf_ctx** out) {
+  if (!p || !out) return PF_ERR_ARG;
+  *out = nullptr;
+  if (p->dx <= 0.0 || p->M < 0.0 || p->L < 0.0 || p->kappa_c < 0.0 || p->kappa_eta < 0.0)
+    return PF_ERR_ARG;
+  if (p->precision != PF_FP64 && p->precision != PF_MIXED) return PF_ERR_ARG;
+  if (p->method != PF_IMEX_EULER && p->method != PF_ARK436L) return PF_ERR_ARG;
+  if (p->adaptive && p->method != PF_ARK436L) return PF_ERR_ARG;
+  if (p->adaptive && (p->rtol < 0.0 || p->atol <= 0.0)) return PF_ERR_ARG;
+  if (p->mean_strain_mode != 0 && p->mean_strain_mode != 1) return PF_ERR_ARG;
+  if (!pf_size_supported(p->nx) || !pf_size_supported(p->ny) || !pf_size_supported(p->nz))
+    return PF_ERR_UNSUPPORTED_SIZE;
+
+  pf_ctx* c = new (std::nothrow) pf_ctx();
+  if (!c) return PF_ERR_OOM;
+  c->p = *p;
+  if (c->p.max_rejects <= 0) c->p.max_rejects = 10;
+  c->stream = (hipStream_t)stream;
+  hipGetDevice(&c->device);
+  c->mixed = p->precision == PF_MIXED;
+
+  Geo& g = c->g;
+  g.nx = p->nx;
+  g.ny = p->ny;
+  g.nz = p->nz;
+  g.nxh = p->nx / 2 + 1;
+  g.P = (g.nxh + 7) / 8 * 8;
+  g.fs = (long long)g.nz * g.ny * g.P;
+  const double twopi = 6.283185307179586476925286766559;
+  g.kfx = twopi / (p->nx * p->dx);
+  g.kfy = twopi / (p->ny * p->dx);
+  g.kfz = twopi / (p->nz * p->dx);
+  setup_model(c);
+  c->tab = p->method == PF_IMEX_EULER ? table_imex_euler() : table_ark436l();
+  for (int i = 0; i < c->tab.s; ++i) {
+    c->fe_need[i] = fe_needed(c->tab, i);
+    c->fi_need[i] = fi_needed(c->tab, i);
+  }
+
+  const size_t kbytes64 = sizeof(cx<double>) * 4 * (size_t)g.fs;
+  const size_t fe_bytes = (c->mixed ? sizeof(cx<float>) : sizeof(cx<double>)) * 4 * (size_t)g.fs;
+  const size_t tbytes = (c->mixed ? sizeof(cx<float>) : sizeof(cx<double>)) * 7 * (size_t)g.fs;
+  const size_t rbytes = sizeof(double) * 4 * (size_t)g.nx * g.ny * g.nz;
+  c->scratch_bytes = std::max(tbytes, rbytes);
+  pf_status s = PF_OK;
+  s = dalloc(c, (void**)&c->y, kbytes64);
+  if (s == PF_OK) s = dalloc(c, (void**)&c->ynew, kbytes64);
+  for (int i = 0; i < c->tab.s && s == PF_OK; ++i) {
+    if (c->fi_need[i] || i == 0) s = dalloc(c, (void**)&c->FI[i], kbytes64);
+    if (s == PF_OK && (c->fe_need[i] || i == 0)) s = dalloc(c, &c->FE[i], fe_bytes);
+  }
+  if (s == PF_OK) s = dalloc(c, &c->scratch, c->scratch_bytes);
+  if (s == PF_OK) s = dalloc(c, (void**)&c->partial, sizeof(double) * 2 * c->nblk_red);
+  if (s == PF_OK) s = dalloc(c, (void**)&c->red, sizeof(double) * 2);
+  if (s == PF_OK && hipHostMalloc((void**)&c->host_red, sizeof(double) * 2, 0) != hipSuccess) s = PF_ERR_OOM;
+  if (s == PF_OK) s = upload_twiddles(c, 0, g.nz);
+  if (s == PF_OK) s = upload_twiddles(c, 1, g.ny);
+  if (s == PF_OK) s = upload_twiddles(c, 2, g.nx / 2);
+  if (s == PF_OK) s = upload_twiddles(c, 3, g.nx);
+  if (s == PF_OK && (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess))
+    s = PF_ERR_HIP;
+  if (s == PF_OK && hipMemsetAsync(c->y, 0, kbytes64, c->stream) != hipSuccess) s = PF_ERR_HIP;
+  if (s == PF_OK && hipStreamSynchronize(c->stream) != hipSuccess) s = PF_ERR_HIP;
+  if (s != PF_OK) {
+    pf_finalize(c);
+    return s;
+  }
+  std::memset(&c->st, 0, sizeof(c->st));
+  c->dt_next = p->dt0;
+  c->st.dt_min_seen = 1e300;
+  *out = c;
+  return PF_OK;
+}
+
+int64_t pf_kspace_pitch(const pf_ctx* c) { return c ? c->g.P : 0; }
+int64_t pf_workspace_bytes(const pf_ctx* c) { return c ? c->ws_bytes : 0; }
+double pf_get_time(const pf_ctx* c) { return c ? c->t : 0.0; }
+
+pf_status pf_set_dt(pf_ctx* c, double dt) {
+  if (!c || !(dt > 0.0)) return PF_ERR_ARG;
+  c->dt_next = dt;
+  return PF_OK;
+}
+
+static double field_bytes64(const pf_ctx* c) {
+  return (double)c->g.nz * c->g.ny * c->g.nxh * sizeof(cx<double>);
+}
+static double real_bytes64(const pf_ctx* c) { return (double)c->g.nz * c->g.ny * c->g.nx * sizeof(double); }
+
+static pf_status forward3d_fp64(pf_ctx* c, const double* re, cx<double>* out, int nf) {
+  const double fk = field_bytes64(c), fr = real_bytes64(c);
+  prof_begin(c);
+  if (!launch_xpass_r2c(c, re, out, nf)) return PF_ERR_UNSUPPORTED_SIZE;
+  prof_end(c, KC_XR2C, nf * (fk + fr));
+  prof_begin(c);
+  if (!launch_colfft<double, -1, 1>(c, out, out, nf, 1.0)) return PF_ERR_UNSUPPORTED_SIZE;
+  prof_end(c, KC_YFFT, 2 * nf * fk);
+  prof_begin(c);
+  if (!launch_colfft<double, -1, 2>(c, out, out, nf, 1.0)) return PF_ERR_UNSUPPORTED_SIZE;
+  prof_end(c, KC_ZFFT, 2 * nf * fk);
+  if (hipGetLastError() != hipSuccess) return PF_ERR_HIP;
+  return PF_OK;
+}
+
+// inverse with 1/N^3 scaling; `in` is used as the intermediate (overwritten)
+static pf_status inverse3d_fp64(pf_ctx* c, cx<double>* in, double* re, int nf) {
+  const double s = c->mk.inv_n3;
+  const double fk = field_bytes64(c), fr = real_bytes64(c);
+  prof_begin(c);
+  if (!launch_colfft<double, +1, 2>(c, in, in, nf, s)) return PF_ERR_UNSUPPORTED_SIZE;
+  prof_end(c, KC_ZFFT, 2 * nf * fk);
+  prof_begin(c);
+  if (!launch_colfft<double, +1, 1>(c, in, in, nf, 1.0)) return PF_ERR_UNSUPPORTED_SIZE;
+  prof_end(c, KC_YFFT, 2 * nf * fk);
+  prof_begin(c);
+  if (!launch_xpass_c2r(c, in, re, nf, 1.0)) return PF_ERR_UNSUPPORTED_SIZE;
+  prof_end(c, KC_XC2R, nf * (fk + fr));
+  if (hipGetLastError() != hipSuccess) return PF_ERR_HIP;
+  return PF_OK;
+}
+
+pf_status pf_set_state(pf_ctx* c, const double* cfield, const double* eta, int32_t on_device, double t0) {
+  if (!c || !cfield || !eta) return PF_ERR_ARG;
+  const size_t n = (size_t)c->g.nx * c->g.ny * c->g.nz;
+  double* stage = (double*)c->scratch;
+  const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  PF_HIP(hipMemcpyAsync(stage, cfield, n * sizeof(double), kind, c->stream));
+  PF_HIP(hipMemcpyAsync(stage + n, eta, 3 * n * sizeof(double), kind, c->stream));
+  pf_status s = forward3d_fp64(c, stage, c->y, 4);
+  if (s != PF_OK) return s;
+  PF_HIP(hipStreamSynchronize(c->stream));
+  c->t = t0;
+  c->have_state = true;
+  return PF_OK;
+}
+
+pf_status pf_get_state(pf_ctx* c, double* cfield, double* eta, int32_t on_device) {
+  if (!c || !cfield || !eta) return PF_ERR_ARG;
+  const size_t n = (size_t)c->g.nx * c->g.ny * c->g.nz;
+  PF_HIP(hipMemcpyAsync(c->ynew, c->y, sizeof(cx<double>) * 4 * c->g.fs, hipMemcpyDeviceToDevice, c->stream));
+  double* stage = (double*)c->scratch;
+  pf_status s = inverse3d_fp64(c, c->ynew, stage, 4);
+  if (s != PF_OK) return s;
+  const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+  PF_HIP(hipMemcpyAsync(cfield, stage, n * sizeof(double), kind, c->stream));
+  PF_HIP(hipMemcpyAsync(eta, stage + n, 3 * n * sizeof(double), kind, c->stream));
+  PF_HIP(hipStreamSynchronize(c->stream));
+  return PF_OK;
+}
+
+pf_status pf_get_state_hat(pf_ctx* c, void* y_hat) {
+  if (!c || !y_hat) return PF_ERR_ARG;
+  PF_HIP(hipMemcpyAsync(y_hat, c->y, sizeof(cx<double>) * 4 * c->g.fs, hipMemcpyDeviceToDevice, c->stream));
+  PF_HIP(hipStreamSynchronize(c->stream));
+  return PF_OK;
+}
+
+pf_status pf_set_state_hat(pf_ctx* c, const void* y_hat, double t0) {
+  if (!c || !y_hat) return PF_ERR_ARG;
+  PF_HIP(hipMemcpyAsync(c->y, y_hat, sizeof(cx<double>) * 4 * c->g.fs, hipMemcpyDeviceToDevice, c->stream));
+  PF_HIP(hipStreamSynchronize(c->stream));
+  c->t = t0;
+  c->have_state = true;
+  return PF_OK;
+}
+
+pf_status pf_rhs(pf_ctx* c, double t, const void* y_hat, void* fI_hat, void* fE_hat) {
+  (void)t;
+  if (!c || !y_hat || !fI_hat || !fE_hat) return PF_ERR_ARG;
+  pf_status s;
+  if (!c->mixed) {
+    StageArgs<double> sa;
+    std::memset(&sa, 0, sizeof(sa));
+    sa.y = (const cx<double>*)y_hat;
+    sa.FI_out = (cx<double>*)fI_hat;
+    sa.FEc_out = c->mk.fEa != 0.0 ? (cx<double>*)fE_hat : nullptr;
+    s = run_stage<double, double>(c, sa, true, (cx<double>*)fE_hat);
+  } else {
+    StageArgs<float> sa;
+    std::memset(&sa, 0, sizeof(sa));
+    sa.y = (const cx<double>*)y_hat;
+    sa.FI_out = (cx<double>*)fI_hat;
+    cx<float>* fe = (cx<float>*)c->FE[0];
+    sa.FEc_out = c->mk.fEa != 0.0 ? fe : nullptr;
+    s = run_stage<float, float>(c, sa, true, fe);
+    if (s == PF_OK) {
+      k_convert<float, double><<<dim3(1024), dim3(256), 0, c->stream>>>(fe, (cx<double>*)fE_hat, c->g, 4);
+      if (hipGetLastError() != hipSuccess) s = PF_ERR_HIP;
+    }
+  }
+  if (s != PF_OK) return s;
+  PF_HIP(hipStreamSynchronize(c->stream));
+  prof_resolve(c);
+  return PF_OK;
+}
+
+pf_status pf_ark_step(pf_ctx* c, double dt, double* dt_next, double* err_out, int32_t* accepted) {
+  if (!c || !(dt > 0.0) || !std::isfinite(dt)) return PF_ERR_ARG;
+  if (!c->have_state) return PF_ERR_STATE;
+  int n_rhs = 0;
+  pf_status s = c->mixed ? stages_and_finalize<float, float>(c, dt, &n_rhs)
+                         : stages_and_finalize<double, double>(c, dt, &n_rhs);
+  if (s != PF_OK) return s;
+  PF_HIP(hipMemcpyAsync(c->host_red, c->red, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  PF_HIP(hipStreamSynchronize(c->stream));
+  prof_resolve(c);
+  const double n3 = (double)c->g.nx * c->g.ny * c->g.nz;
+  double err = c->tab.has_emb ? std::sqrt(c->host_red[0] / (4.0 * n3)) : 0.0;
+  const bool finite = c->host_red[1] == 0.0 && std::isfinite(err);
+  if (!finite) err = INFINITY;
+  bool ok;
+  double nxt;
+  if (c->p.adaptive) {
+    ok = finite && err <= 1.0;
+    nxt = std::max(controller(dt, err, c->tab.emb_order, !ok), c->p.dt_min);
+  } else {
+    ok = finite;
+    nxt = c->p.dt0;
+  }
+  c->st.attempts += 1;
+  c->st.n_rhs += n_rhs;
+  c->st.err_last = err;
+  if (ok) {
+    std::swap(c->y, c->ynew);
+    c->t += dt;
+    c->st.steps += 1;
+    c->st.dt_last = dt;
+    c->st.dt_min_seen = std::min(c->st.dt_min_seen, dt);
+    c->st.dt_max_seen = std::max(c->st.dt_max_seen, dt);
+  } else {
+    c->st.rejects += 1;
+  }
+  c->dt_next = nxt;
+  c->st.dt_next = nxt;
+  c->st.t = c->t;
+  if (dt_next) *dt_next = nxt;
+  if (err_out) *err_out = err;
+  if (accepted) *accepted = ok ? 1 : 0;
+  if (!finite && !c->p.adaptive) return PF_ERR_NONFINITE;
+  return PF_OK;
+}
+
+pf_status pf_get_stats(pf_ctx* c, pf_stats* out) {
+  if (!c || !out) return PF_ERR_ARG;
+  cx<double> c0;
+  PF_HIP(hipMemcpyAsync(&c0, c->y, sizeof(c0), hipMemcpyDeviceToHost, c->stream));
+  PF_HIP(hipStreamSynchronize(c->stream));
+  c->st.mass = c0.re * c->mk.inv_n3;
+  c->st.t = c->t;
+  *out = c->st;
+  return PF_OK;
+}
+
+pf_status pf_advance(pf_ctx* c, double t_final, pf_stats* out) {
+  if (!c) return PF_ERR_ARG;
+  if (!c->have_state) return PF_ERR_STATE;
+  PF_HIP(hipEventRecord(c->ev0, c->stream));
+  int rejects = 0;
+  pf_status s = PF_OK;
+  while (c->t < t_final * (1.0 - 1e-15)) {
+    double dt = c->p.adaptive ? std::min(c->dt_next, c->p.dt_max) : std::min(c->p.dt0, c->p.dt_max);
+    dt = std::min(dt, t_final - c->t);
+    int32_t acc = 0;
+    s = pf_ark_step(c, dt, nullptr, nullptr, &acc);
+    if (s != PF_OK) break;
+    if (acc) {
+      rejects = 0;
+    } else if (++rejects >= c->p.max_rejects) {
+      s = PF_ERR_STEP_FAIL;
+      break;
+    }
+  }
+  PF_HIP(hipEventRecord(c->ev1, c->stream));
+  PF_HIP(hipEventSynchronize(c->ev1));
+  float ms = 0.f;
+  hipEventElapsedTime(&ms, c->ev0, c->ev1);
+  c->st.elapsed_ms += ms;
+  if (out) {
+    pf_status s2 = pf_get_stats(c, out);
+    if (s == PF_OK) s = s2;
+  }
+  return s;
+}
+
+pf_status pf_diagnostics(pf_ctx* c, double* mass, double* vf, double* vf_thr) {
+  if (!c) return PF_ERR_ARG;
+  const long long n = (long long)c->g.nx * c->g.ny * c->g.nz;
+  PF_HIP(hipMemcpyAsync(c->ynew, c->y, sizeof(cx<double>) * 4 * c->g.fs, hipMemcpyDeviceToDevice, c->stream));
+  double* stage = (double*)c->scratch;
+  pf_status s = inverse3d_fp64(c, c->ynew, stage, 4);
+  if (s != PF_OK) return s;
+  k_vf_partial<<<dim3(c->nblk_red), dim3(256), 0, c->stream>>>(stage, n, c->partial);
+  k_reduce_pairs<<<dim3(1), dim3(256), 0, c->stream>>>(c->partial, c->nblk_red, c->red);
+  PF_HIP(hipGetLastError());
+  PF_HIP(hipMemcpyAsync(c->host_red, c->red, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  cx<double> c0;
+  PF_HIP(hipMemcpyAsync(&c0, c->y, sizeof(c0), hipMemcpyDeviceToHost, c->stream));
+  PF_HIP(hipStreamSynchronize(c->stream));
+  if (mass) *mass = c0.re / (double)n;
+  if (vf) *vf = c->host_red[0] / (double)n;
+  if (vf_thr) *vf_thr = c->host_red[1] / (double)n;
+  return PF_OK;
+}
+
+pf_status pf_fft3d(pf_ctx* c, int32_t dir, int32_t nf, void* in, void* out) {
+  if (!c || !in || !out || nf < 1 || nf > 4 || (dir != -1 && dir != 1)) return PF_ERR_ARG;
+  pf_status s = dir < 0 ? forward3d_fp64(c, (const double*)in, (cx<double>*)out, nf)
+                        : inverse3d_fp64(c, (cx<double>*)in, (double*)out, nf);
+  if (s != PF_OK) return s;
+  PF_HIP(hipStreamSynchronize(c->stream));
+  prof_resolve(c);
+  return PF_OK;
+}
+
+pf_status pf_profile_enable(pf_ctx* c, int32_t on) {
+  if (!c) return PF_ERR_ARG;
+  PF_HIP(hipStreamSynchronize(c->stream));
+  c->prof_pending.clear();
+  c->prof_used = 0;
+  for (int k = 0; k < 16; ++k) {
+    c->prof_ms[k] = 0.0;
+    c->prof_bytes[k] = 0.0;
+    c->prof_n[k] = 0;
+  }
+  c->prof_on = on != 0;
+  return PF_OK;
+}
+
+int32_t pf_profile_classes(void) { return KC_COUNT; }
+
+const char* pf_profile_name(int32_t cls) {
+  if (cls < 0 || cls >= KC_COUNT) return "";
+  return kc_names[cls];
+}
+
+pf_status pf_profile_get(pf_ctx* c, int32_t cls, double* total_ms, int64_t* launches, double* bytes) {
+  if (!c || cls < 0 || cls >= KC_COUNT) return PF_ERR_ARG;
+  if (total_ms) *total_ms = c->prof_ms[cls];
+  if (launches) *launches = c->prof_n[cls];
+  if (bytes) *bytes = c->prof_bytes[cls];
+  return PF_OK;
+}
+
+}  // extern "C"

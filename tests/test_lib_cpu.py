@@ -1,0 +1,72 @@
+"""Host-only checks of libpf: it loads without a GPU and exports every symbol pf.h declares."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pf.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(pf_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2609_36100_amd import _lib
+    L = _lib.lib()
+    names = _declared()
+    assert len(names) >= 18
+    for n in names:
+        assert hasattr(L, n), n
+    # the Python binding binds exactly the declared entry points
+    assert sorted(_lib.exported_symbols()) == names
+
+
+def test_host_only_entry_points():
+    from paper_2609_36100_amd import _lib
+    L = _lib.lib()
+    p = _lib.Params()
+    assert L.pf_default_params(ctypes.byref(p)) == 0
+    assert (p.C11, p.C12, p.C44) == (250.0, 150.0, 120.0)
+    assert p.eps_star[1][1] == 0.0286 and p.eps_star[1][0] == 0.0067
+    for n in (8, 16, 24, 32, 48, 64, 96, 128, 256, 512):
+        assert L.pf_size_supported(n) == 1, n
+    for n in (6, 10, 12, 168, 336, 504, 1024, 7, 0, -8):
+        assert L.pf_size_supported(n) == 0, n
+    assert L.pf_status_string(-4) == b"PF_ERR_UNSUPPORTED_SIZE"
+    assert L.pf_status_string(12345) == b"PF_UNKNOWN_STATUS"
+    assert L.pf_init(None, None, None) == -1
+
+
+def test_params_struct_matches_header_layout():
+    """sizeof(pf_params) / sizeof(pf_stats) seen by ctypes equal the C compiler's."""
+    from paper_2609_36100_amd import _lib
+    src = ('#include "pf.h"\n#include <stdio.h>\n'
+           'int main(){printf("%zu %zu\\n", sizeof(pf_params), sizeof(pf_stats));return 0;}\n')
+    exe = "/tmp/pf_sizeof_check"
+    r = subprocess.run(["gcc", "-x", "c", "-I", os.path.join(ROOT, "include"), "-o", exe, "-"],
+                       input=src, text=True, capture_output=True)
+    assert r.returncode == 0, r.stderr
+    out = subprocess.run([exe], capture_output=True, text=True).stdout.split()
+    assert int(out[0]) == ctypes.sizeof(_lib.Params)
+    assert int(out[1]) == ctypes.sizeof(_lib.Stats)
+
+
+def test_fft_building_blocks_on_host():
+    """Plans, radix DFTs, Stockham indexing and r2c/c2r packing against a naive DFT."""
+    exe = "/tmp/pf_fft_host_check"
+    r = subprocess.run(["hipcc", "--offload-arch=gfx950", "-O2", "-std=c++17", "-o", exe,
+                        os.path.join(ROOT, "tests", "native", "fft_host_check.cpp")],
+                       capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr[-2000:]
+    out = subprocess.run([exe], capture_output=True, text=True)
+    assert out.returncode == 0, out.stdout
+    lines = [l.split() for l in out.stdout.strip().splitlines()]
+    assert len(lines) >= 60
+    for name, n, err in lines:
+        assert float(err) < 1e-14, (name, n, err)
