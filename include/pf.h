@@ -190,6 +190,21 @@ int32_t pf_profile_classes(void);
 const char* pf_profile_name(int32_t cls);
 pf_status pf_profile_get(pf_ctx* ctx, int32_t cls, double* total_ms, int64_t* launches, double* bytes);
 
+/* Autotuner for the FFT tile plans.  Every column (y/z) pass kind
+ * ("colfft", "stage_invz", "zpass_elastic", "zpass_fwd_ac") has two tile
+ * variants (kx columns per work-group; see pf_tuning_get).  pf_autotune
+ * times each variant `reps` times on this context's own buffers and keeps the
+ * faster one; it overwrites the stage derivative arrays (call it between
+ * steps, never inside one) and leaves the state untouched.  pf_tuning_set
+ * forces a variant (0 or 1).  Kinds are 0 .. pf_tuning_kinds()-1;
+ * pf_tuning_name never returns NULL ("" for an invalid kind). */
+pf_status pf_autotune(pf_ctx* ctx, int32_t reps);
+int32_t pf_tuning_kinds(void);
+const char* pf_tuning_name(int32_t kind);
+pf_status pf_tuning_get(pf_ctx* ctx, int32_t kind, int32_t* variant, int32_t* tile_cols,
+                        int32_t* end_radix, double* ms_v0, double* ms_v1);
+pf_status pf_tuning_set(pf_ctx* ctx, int32_t kind, int32_t variant);
+
 /* Human-readable status name; never NULL. */
 const char* pf_status_string(pf_status s);
 

@@ -160,6 +160,27 @@ class Solver:
                    "pf_diagnostics")
         return dict(mass=m.value, vf=v.value, vf_threshold=vt.value)
 
+    # -- tile plans -------------------------------------------------------------
+    def autotune(self, reps=3):
+        """Time both tile variants of every column pass and keep the faster ones."""
+        _lib.check(_lib.lib().pf_autotune(self._h, int(reps)), "pf_autotune")
+        return self.tuning()
+
+    def tuning(self):
+        L = _lib.lib()
+        out = {}
+        for k in range(L.pf_tuning_kinds()):
+            v, tx, re_ = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+            m0, m1 = ctypes.c_double(), ctypes.c_double()
+            _lib.check(L.pf_tuning_get(self._h, k, ctypes.byref(v), ctypes.byref(tx), ctypes.byref(re_),
+                                       ctypes.byref(m0), ctypes.byref(m1)), "pf_tuning_get")
+            out[L.pf_tuning_name(k).decode()] = dict(variant=v.value, tile_cols=tx.value,
+                                                     end_radix=re_.value, ms=[m0.value, m1.value])
+        return out
+
+    def set_tuning(self, kind, variant):
+        _lib.check(_lib.lib().pf_tuning_set(self._h, int(kind), int(variant)), "pf_tuning_set")
+
     # -- measurement ----------------------------------------------------------
     def profile(self, on=True):
         """Clear and enable/disable per-kernel-class HIP-event timing."""

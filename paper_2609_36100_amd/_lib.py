@@ -84,6 +84,13 @@ _SIGS = {
                                       ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
     "pf_fft3d": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]),
     "pf_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "pf_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
+    "pf_tuning_kinds": (ctypes.c_int32, []),
+    "pf_tuning_name": (ctypes.c_char_p, [ctypes.c_int32]),
+    "pf_tuning_get": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                     ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                                     ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
+    "pf_tuning_set": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32]),
     "pf_profile_enable": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "pf_profile_classes": (ctypes.c_int32, []),
     "pf_profile_name": (ctypes.c_char_p, [ctypes.c_int32]),

@@ -164,15 +164,18 @@ struct Plan {
   int ok;      // 1 when n is supported
 };
 
-__host__ __device__ constexpr Plan plan(int n) {
+// Radix sequence for a line of length n whose first and last radix (the "end"
+// radix, at most remax) are equal.  Middle factors are taken greedily from
+// {8, 4, 2, 3, 5}.  ok = 0 when n has no such factorisation.
+__host__ __device__ constexpr Plan plan(int n, int remax = 8) {
   Plan P{n, 0, {0, 0, 0, 0, 0, 0, 0, 0}, 0};
-  if (n == 2 || n == 3 || n == 4 || n == 5 || n == 8) {
+  if (n == 3 || n == 5 || ((n == 2 || n == 4 || n == 8) && n <= remax)) {
     P.np = 1;
     P.r[0] = n;
     P.ok = 1;
     return P;
   }
-  int re = (n % 64 == 0) ? 8 : (n % 16 == 0) ? 4 : (n % 4 == 0) ? 2 : 0;
+  int re = (remax >= 8 && n % 64 == 0) ? 8 : (remax >= 4 && n % 16 == 0) ? 4 : (n % 4 == 0) ? 2 : 0;
   if (re == 0) return P;
   int m = n / (re * re);
   int mid[6] = {0, 0, 0, 0, 0, 0};
@@ -192,7 +195,7 @@ __host__ __device__ constexpr Plan plan(int n) {
 }
 
 // Threads cooperating on one line: one butterfly each in the first/last pass.
-__host__ __device__ constexpr int line_threads(int n) { return n / plan(n).r[0]; }
+__host__ __device__ constexpr int line_threads(int n, int remax = 8) { return n / plan(n, remax).r[0]; }
 
 // Largest number of values a thread holds in any pass (registers per line).
 __host__ __device__ constexpr int line_regs(int n) {

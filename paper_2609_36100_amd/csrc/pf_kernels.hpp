@@ -102,22 +102,49 @@ __device__ inline void elastic_apply(const ModelK& m, R kx, R ky, R kz, const cx
   }
 }
 
+// Multiply a[t] by w^{S t j} (t = 1..R-1) where w^{-m} = tw[m]; only the
+// powers 1, 2 (and 4) come from the table, the others are products of two
+// table values (a few ulp).
+template <int R, int S, typename T>
+__device__ inline void apply_twiddles(cx<T>* a, const cx<T>* tw, int j) {
+  if constexpr (R == 2) {
+    a[1] = cmul(a[1], twiddle<S>(tw, j));
+  } else {
+    const cx<T> w1 = twiddle<S>(tw, j), w2 = twiddle<S>(tw, 2 * j);
+    a[1] = cmul(a[1], w1);
+    a[2] = cmul(a[2], w2);
+    if constexpr (R >= 4) {
+      const cx<T> w3 = cmul(w1, w2);
+      a[3] = cmul(a[3], w3);
+      if constexpr (R == 5) {
+        a[4] = cmul(a[4], cmul(w2, w2));
+      } else if constexpr (R == 8) {
+        const cx<T> w4 = twiddle<S>(tw, 4 * j);
+        a[4] = cmul(a[4], w4);
+        a[5] = cmul(a[5], cmul(w4, w1));
+        a[6] = cmul(a[6], cmul(w4, w2));
+        a[7] = cmul(a[7], cmul(w4, w3));
+      }
+    }
+  }
+}
+
 // ---- line FFT in LDS -------------------------------------------------------
-__host__ __device__ constexpr int plan_prod(int n, int q) {
-  Plan P = plan(n);
+__host__ __device__ constexpr int plan_prod(int n, int q, int re) {
+  Plan P = plan(n, re);
   int p = 1;
   for (int i = 0; i < q; ++i) p *= P.r[i];
   return p;
 }
 
-template <typename T, int N, int S, int Q>
+template <typename T, int N, int S, int Q, int RE>
 struct MidPass {
   template <class Buf>
   __device__ static inline void run(int tid, const cx<T>* tw, Buf buf) {
-    constexpr Plan PL = plan(N);
+    constexpr Plan PL = plan(N, RE);
     if constexpr (Q < PL.np - 1) {
       constexpr int r = PL.r[Q];
-      constexpr int p = plan_prod(N, Q);
+      constexpr int p = plan_prod(N, Q, RE);
       constexpr int TL = N / PL.r[0];
       constexpr int NB = N / r;
       constexpr int PER = (NB + TL - 1) / TL;
@@ -130,8 +157,7 @@ struct MidPass {
 #pragma unroll
           for (int t = 0; t < r; ++t) v[j][t] = buf(b + t * NB);
           constexpr int step = N / (p * r);
-#pragma unroll
-          for (int t = 1; t < r; ++t) v[j][t] = cmul(v[j][t], twiddle<S>(tw, t * k * step));
+          apply_twiddles<r, S>(v[j], tw, k * step);
           dft<r, S>(v[j]);
         }
       }
@@ -146,18 +172,19 @@ struct MidPass {
         }
       }
       __syncthreads();
-      MidPass<T, N, S, Q + 1>::run(tid, tw, buf);
+      MidPass<T, N, S, Q + 1, RE>::run(tid, tw, buf);
     }
   }
 };
 
-// In-place FFT of one line of length N by TL = N / r0 cooperating threads.
-// On entry a[t] holds x[tid + t N/r0]; on exit X[tid + t N/r0].  Every thread
-// of the work-group must call this the same number of times (it contains
-// work-group barriers); the LDS region behind `buf` must hold N values.
-template <typename T, int N, int S, class Buf>
+// In-place FFT of one line of length N by TL = N / r0 cooperating threads
+// (r0 = the plan's end radix, at most RE).  On entry a[t] holds
+// x[tid + t N/r0]; on exit X[tid + t N/r0].  Every thread of the work-group
+// must call this the same number of times (it contains work-group barriers);
+// the LDS region behind `buf` must hold N values.
+template <typename T, int N, int S, int RE = 8, class Buf>
 __device__ inline void line_fft(cx<T>* a, int tid, const cx<T>* tw, Buf buf) {
-  constexpr Plan PL = plan(N);
+  constexpr Plan PL = plan(N, RE);
   static_assert(PL.ok, "unsupported line length");
   constexpr int R0 = PL.r[0];
   constexpr int TL = N / R0;
@@ -167,14 +194,22 @@ __device__ inline void line_fft(cx<T>* a, int tid, const cx<T>* tw, Buf buf) {
 #pragma unroll
     for (int t = 0; t < R0; ++t) buf(tid * R0 + t) = a[t];
     __syncthreads();
-    MidPass<T, N, S, 1>::run(tid, tw, buf);
+    MidPass<T, N, S, 1, RE>::run(tid, tw, buf);
 #pragma unroll
     for (int t = 0; t < R0; ++t) a[t] = buf(tid + t * TL);
     // last pass: p = N / R0, k = tid, twiddle w_N^{t tid}
-#pragma unroll
-    for (int t = 1; t < R0; ++t) a[t] = cmul(a[t], twiddle<S>(tw, t * tid));
+    apply_twiddles<R0, S>(a, tw, tid);
     dft<R0, S>(a);
   }
+}
+
+// Work-groups are handed to the 8 XCDs round-robin.  Renumber them so each
+// XCD processes a contiguous run of logical tiles: neighbouring column
+// bundles (which share cache lines) then meet in the same L2.
+__device__ inline int xcd_tile(int b, int nb) {
+  const int q = nb >> 3, r = nb & 7;
+  const int xcd = b & 7, slot = b >> 3;
+  return xcd < r ? xcd * (q + 1) + slot : r * (q + 1) + (xcd - r) * q + slot;
 }
 
 template <typename T>
@@ -186,9 +221,9 @@ template <typename T>
 __device__ inline cx<double> to_d(cx<T> z) { return mk<double>((double)z.re, (double)z.im); }
 
 // ---- column-pass geometry -----------------------------------------------
-template <int N, int TX>
+template <int N, int TX, int RE>
 struct ColGeo {
-  static constexpr int R0 = plan(N).r[0];
+  static constexpr int R0 = plan(N, RE).r[0];
   static constexpr int TL = N / R0;
   static constexpr int THREADS = TX * TL;
   static constexpr int LD = TX + 1;  // LDS row pitch (padding)
@@ -207,15 +242,35 @@ struct StageArgs {
   cx<TE>* FEc_out;         // split A: explicit CH part from z_c (may be null)
 };
 
-template <typename T, typename TE, int N, int TX>
-__global__ void __launch_bounds__((ColGeo<N, TX>::THREADS))
-k_stage_invz(StageArgs<TE> sa, Geo g, ModelK m, const cx<T>* __restrict__ twz,
-             cx<T>* __restrict__ out, int do_fft) {
-  using CG = ColGeo<N, TX>;
+// Stage combination for one element (Eq. ARK_stage restricted to the
+// previous stages), then the implicit solve z = r / (1 - dt A^I_ii L(k)).
+template <typename TE, int NP>
+__device__ inline cx<double> stage_value(const StageArgs<TE>& sa, long long idx, double L, cx<double>* FIo,
+                                         cx<TE>* FEo, double fea_k2, int f) {
+  cx<double> r = sa.y[idx];
+  cx<double> fe[NP > 0 ? NP : 1], fi[NP > 0 ? NP : 1];
+#pragma unroll
+  for (int j = 0; j < NP; ++j) {
+    fe[j] = sa.cE[j] != 0.0 ? to_d(sa.FE[j][idx]) : mk(0.0, 0.0);
+    fi[j] = sa.cI[j] != 0.0 ? sa.FI[j][idx] : mk(0.0, 0.0);
+  }
+#pragma unroll
+  for (int j = 0; j < NP; ++j) r = r + (sa.cE[j] * fe[j] + sa.cI[j] * fi[j]);
+  const cx<double> zz = (sa.gdt != 0.0) ? (1.0 / (1.0 - sa.gdt * L)) * r : r;
+  if (FIo) FIo[idx] = L * zz;
+  if (f == 0 && FEo) FEo[idx] = to_t<TE>((-fea_k2) * zz);
+  return zz;
+}
+
+template <typename T, typename TE, int N, int TX, int RE, int NP>
+__global__ void __launch_bounds__((ColGeo<N, TX, RE>::THREADS))
+k_stage_invz(StageArgs<TE> sa, Geo g, ModelK m, const cx<T>* twz, cx<T>* __restrict__ out) {
+  using CG = ColGeo<N, TX, RE>;
   __shared__ cx<T> lds[N * CG::LD];
   const int nbx = (g.nxh + TX - 1) / TX;
-  const int xb = blockIdx.x % nbx;
-  const int y = blockIdx.x / nbx;
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int xb = tile % nbx;
+  const int y = tile / nbx;
   const int col = threadIdx.x % TX;
   const int bf = threadIdx.x / TX;
   const int x = xb * TX + col;
@@ -224,51 +279,74 @@ k_stage_invz(StageArgs<TE> sa, Geo g, ModelK m, const cx<T>* __restrict__ twz,
   const double ky = mode_of(y, g.ny) * g.kfy;
   auto buf = [&](int pos) -> cx<T>& { return lds[pos * CG::LD + col]; };
   for (int f = 0; f < 4; ++f) {
-    cx<T> a[CG::R0];
-#pragma unroll
+    // combine + solve position by position into LDS (bounded unroll keeps the
+    // stage-array loads of a few positions in flight, not all of them)
+    __syncthreads();
+#pragma unroll 2
     for (int t = 0; t < CG::R0; ++t) {
       const int z = bf + t * CG::TL;
       const long long idx = f * g.fs + ((long long)z * g.ny + y) * g.P + x;
       cx<double> r = mk(0.0, 0.0);
       if (valid) {
-        r = sa.y[idx];
-        for (int j = 0; j < sa.nprev; ++j) {
-          if (sa.cE[j] != 0.0) r = r + sa.cE[j] * to_d(sa.FE[j][idx]);
-          if (sa.cI[j] != 0.0) r = r + sa.cI[j] * sa.FI[j][idx];
-        }
         const double kz = mode_of(z, g.nz) * g.kfz;
         const double k2 = kx * kx + ky * ky + kz * kz;
-        const double L = lsym(m, f, k2);
-        const cx<double> zz = (sa.gdt != 0.0) ? (1.0 / (1.0 - sa.gdt * L)) * r : r;
-        if (sa.FI_out) sa.FI_out[idx] = L * zz;
-        if (f == 0 && sa.FEc_out) sa.FEc_out[idx] = to_t<TE>((-m.fEa * k2) * zz);
-        r = m.inv_n3 * zz;
+        r = m.inv_n3 * stage_value<TE, NP>(sa, idx, lsym(m, f, k2), sa.FI_out, sa.FEc_out, m.fEa * k2, f);
       }
-      a[t] = to_t<T>(r);
+      buf(z) = to_t<T>(r);
     }
-    if (do_fft) {
-      line_fft<T, N, +1>(a, bf, twz, buf);
-      if (valid) {
+    __syncthreads();
+    cx<T> a[CG::R0];
 #pragma unroll
-        for (int t = 0; t < CG::R0; ++t) {
-          const int z = bf + t * CG::TL;
-          out[f * g.fs + ((long long)z * g.ny + y) * g.P + x] = a[t];
-        }
+    for (int t = 0; t < CG::R0; ++t) a[t] = buf(bf + t * CG::TL);
+    line_fft<T, N, +1, RE>(a, bf, twz, buf);
+    if (valid) {
+#pragma unroll
+      for (int t = 0; t < CG::R0; ++t) {
+        const int z = bf + t * CG::TL;
+        out[f * g.fs + ((long long)z * g.ny + y) * g.P + x] = a[t];
       }
     }
   }
 }
 
+// Stage combination and implicit solve only (a stage whose explicit
+// derivative is never used, e.g. the implicit stage of IMEX Euler).
+template <typename TE>
+__global__ void __launch_bounds__(256) k_combine(StageArgs<TE> sa, Geo g, ModelK m) {
+  const long long nrow = (long long)g.nz * g.ny;
+  const long long total = 4 * nrow * g.nxh;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
+       i += (long long)gridDim.x * blockDim.x) {
+    const int x = (int)(i % g.nxh);
+    const long long fr = i / g.nxh;
+    const int f = (int)(fr / nrow);
+    const long long row = fr % nrow;
+    const int y = (int)(row % g.ny), z = (int)(row / g.ny);
+    const double kx = x * g.kfx, ky = mode_of(y, g.ny) * g.kfy, kz = mode_of(z, g.nz) * g.kfz;
+    const double k2 = kx * kx + ky * ky + kz * kz;
+    const long long idx = fr * g.P + x;
+    cx<double> r = sa.y[idx];
+    for (int j = 0; j < sa.nprev; ++j) {
+      if (sa.cE[j] != 0.0) r = r + sa.cE[j] * to_d(sa.FE[j][idx]);
+      if (sa.cI[j] != 0.0) r = r + sa.cI[j] * sa.FI[j][idx];
+    }
+    const double L = lsym(m, f, k2);
+    const cx<double> zz = (sa.gdt != 0.0) ? (1.0 / (1.0 - sa.gdt * L)) * r : r;
+    if (sa.FI_out) sa.FI_out[idx] = L * zz;
+  }
+}
+
 // ---- generic column FFT along y or z (in or out of place) -----------------
 // axis 1 = y (lines at fixed z), axis 2 = z (lines at fixed y).
-template <typename T, int N, int TX, int S, int AXIS>
-__global__ void __launch_bounds__((ColGeo<N, TX>::THREADS))
-k_colfft(const cx<T>* in, cx<T>* out, Geo g, int nf, const cx<T>* __restrict__ tw, T scale) {
-  using CG = ColGeo<N, TX>;
+template <typename T, int N, int TX, int RE, int S, int AXIS>
+__global__ void __launch_bounds__((ColGeo<N, TX, RE>::THREADS))
+k_colfft(const cx<T>* in, cx<T>* out, Geo g, int nf, const cx<T>* tw, T scale) {
+  using CG = ColGeo<N, TX, RE>;
   __shared__ cx<T> lds[N * CG::LD];
   const int nbx = (g.nxh + TX - 1) / TX;
-  const int xb = blockIdx.x % nbx;
-  const int o = blockIdx.x / nbx;  // fixed z (AXIS 1) or fixed y (AXIS 2)
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int xb = tile % nbx;
+  const int o = tile / nbx;  // fixed z (AXIS 1) or fixed y (AXIS 2)
   const int col = threadIdx.x % TX;
   const int bf = threadIdx.x / TX;
   const int x = xb * TX + col;
@@ -284,7 +362,7 @@ k_colfft(const cx<T>* in, cx<T>* out, Geo g, int nf, const cx<T>* __restrict__ t
       const int q = bf + t * CG::TL;
       a[t] = valid ? in[fb + q * lstride] : mk<T>(0, 0);
     }
-    line_fft<T, N, S>(a, bf, tw, buf);
+    line_fft<T, N, S, RE>(a, bf, tw, buf);
     if (valid) {
 #pragma unroll
       for (int t = 0; t < CG::R0; ++t) {
@@ -296,15 +374,16 @@ k_colfft(const cx<T>* in, cx<T>* out, Geo g, int nf, const cx<T>* __restrict__ t
 }
 
 // ---- K-E: forward z-FFT of theta, elastic solve, explicit CH, inverse z ----
-template <typename T, typename TE, int N, int TX>
-__global__ void __launch_bounds__((ColGeo<N, TX>::THREADS))
-k_zpass_elastic(cx<T>* __restrict__ th, Geo g, ModelK m, const cx<T>* __restrict__ twz,
+template <typename T, typename TE, int N, int TX, int RE>
+__global__ void __launch_bounds__((ColGeo<N, TX, RE>::THREADS))
+k_zpass_elastic(cx<T>* __restrict__ th, Geo g, ModelK m, const cx<T>* twz,
                 cx<TE>* __restrict__ FEc, int accumulate) {
-  using CG = ColGeo<N, TX>;
+  using CG = ColGeo<N, TX, RE>;
   __shared__ cx<T> lds[N * CG::LD];
   const int nbx = (g.nxh + TX - 1) / TX;
-  const int xb = blockIdx.x % nbx;
-  const int y = blockIdx.x / nbx;
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int xb = tile % nbx;
+  const int y = tile / nbx;
   const int col = threadIdx.x % TX;
   const int bf = threadIdx.x / TX;
   const int x = xb * TX + col;
@@ -320,7 +399,7 @@ k_zpass_elastic(cx<T>* __restrict__ th, Geo g, ModelK m, const cx<T>* __restrict
       const int z = bf + t * CG::TL;
       a[v][t] = valid ? th[v * g.fs + base + z * lstride] : mk<T>(0, 0);
     }
-    line_fft<T, N, -1>(a[v], bf, twz, buf);
+    line_fft<T, N, -1, RE>(a[v], bf, twz, buf);
   }
   const T kx = (T)(x * g.kfx);
   const T ky = (T)(mode_of(y, g.ny) * g.kfy);
@@ -357,10 +436,12 @@ k_zpass_elastic(cx<T>* __restrict__ th, Geo g, ModelK m, const cx<T>* __restrict
     const T s = (T)m.inv_n3;
 #pragma unroll
     for (int v = 0; v < 3; ++v) a[v][t] = s * e[v];
+    // one mode at a time: interleaving the solves only raises register pressure
+    __builtin_amdgcn_sched_barrier(0);
   }
 #pragma unroll
   for (int v = 0; v < 3; ++v) {
-    line_fft<T, N, +1>(a[v], bf, twz, buf);
+    line_fft<T, N, +1, RE>(a[v], bf, twz, buf);
     if (valid) {
 #pragma unroll
       for (int t = 0; t < CG::R0; ++t) {
@@ -372,15 +453,16 @@ k_zpass_elastic(cx<T>* __restrict__ th, Geo g, ModelK m, const cx<T>* __restrict
 }
 
 // ---- K-I: forward z-FFT of the AC driving force, F^E_eta = -L g~ ----------
-template <typename T, typename TE, int N, int TX>
-__global__ void __launch_bounds__((ColGeo<N, TX>::THREADS))
-k_zpass_fwd_ac(const cx<T>* __restrict__ gk, Geo g, ModelK m, const cx<T>* __restrict__ twz,
+template <typename T, typename TE, int N, int TX, int RE>
+__global__ void __launch_bounds__((ColGeo<N, TX, RE>::THREADS))
+k_zpass_fwd_ac(const cx<T>* __restrict__ gk, Geo g, ModelK m, const cx<T>* twz,
                cx<TE>* __restrict__ FE) {
-  using CG = ColGeo<N, TX>;
+  using CG = ColGeo<N, TX, RE>;
   __shared__ cx<T> lds[N * CG::LD];
   const int nbx = (g.nxh + TX - 1) / TX;
-  const int xb = blockIdx.x % nbx;
-  const int y = blockIdx.x / nbx;
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int xb = tile % nbx;
+  const int y = tile / nbx;
   const int col = threadIdx.x % TX;
   const int bf = threadIdx.x / TX;
   const int x = xb * TX + col;
@@ -396,7 +478,7 @@ k_zpass_fwd_ac(const cx<T>* __restrict__ gk, Geo g, ModelK m, const cx<T>* __res
       const int z = bf + t * CG::TL;
       a[t] = valid ? gk[v * g.fs + base + z * lstride] : mk<T>(0, 0);
     }
-    line_fft<T, N, -1>(a, bf, twz, buf);
+    line_fft<T, N, -1, RE>(a, bf, twz, buf);
     if (valid) {
 #pragma unroll
       for (int t = 0; t < CG::R0; ++t) {
@@ -482,7 +564,7 @@ __device__ inline T dhfun(T e) {
 template <typename T, int M, int RB>
 __global__ void __launch_bounds__((RowGeo<M, RB>::THREADS))
 k_xpass_theta(const cx<T>* __restrict__ st, cx<T>* __restrict__ th, Geo g,
-              const cx<T>* __restrict__ twN, const cx<T>* __restrict__ twM) {
+              const cx<T>* twN, const cx<T>* twM) {
   using RG = RowGeo<M, RB>;
   __shared__ cx<T> lds[RB * RG::LD];
   const int rl = threadIdx.x / RG::TL;
@@ -504,7 +586,7 @@ k_xpass_theta(const cx<T>* __restrict__ st, cx<T>* __restrict__ th, Geo g,
 template <typename T, int M, int RB>
 __global__ void __launch_bounds__((RowGeo<M, RB>::THREADS))
 k_xpass_drive(const cx<T>* __restrict__ st, cx<T>* __restrict__ el, Geo g, ModelK m,
-              const cx<T>* __restrict__ twN, const cx<T>* __restrict__ twM) {
+              const cx<T>* twN, const cx<T>* twM) {
   using RG = RowGeo<M, RB>;
   __shared__ cx<T> lds[RB * RG::LD];
   const int rl = threadIdx.x / RG::TL;
@@ -544,7 +626,7 @@ k_xpass_drive(const cx<T>* __restrict__ st, cx<T>* __restrict__ el, Geo g, Model
 template <typename T, int M, int RB>
 __global__ void __launch_bounds__((RowGeo<M, RB>::THREADS))
 k_xpass_r2c(const T* __restrict__ re, cx<T>* __restrict__ out, Geo g, int nf,
-            const cx<T>* __restrict__ twN, const cx<T>* __restrict__ twM) {
+            const cx<T>* twN, const cx<T>* twM) {
   using RG = RowGeo<M, RB>;
   __shared__ cx<T> lds[RB * RG::LD];
   const int rl = threadIdx.x / RG::TL;
@@ -567,7 +649,7 @@ k_xpass_r2c(const T* __restrict__ re, cx<T>* __restrict__ out, Geo g, int nf,
 template <typename T, int M, int RB>
 __global__ void __launch_bounds__((RowGeo<M, RB>::THREADS))
 k_xpass_c2r(const cx<T>* __restrict__ in, T* __restrict__ re, Geo g, int nf, T scale,
-            const cx<T>* __restrict__ twN, const cx<T>* __restrict__ twM) {
+            const cx<T>* twN, const cx<T>* twM) {
   using RG = RowGeo<M, RB>;
   __shared__ cx<T> lds[RB * RG::LD];
   const int rl = threadIdx.x / RG::TL;

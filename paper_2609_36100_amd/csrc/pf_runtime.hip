@@ -62,9 +62,30 @@ static bool row_supported(int m) {
   return row_dispatch(m, [](auto) {});
 }
 
-// Columns per column-pass work-group: 128 contiguous bytes per row segment.
-template <typename T>
-constexpr int tx_of() { return sizeof(T) == 8 ? 8 : 16; }
+// Column-pass tiles: TX consecutive kx columns per work-group, end radix RE.
+// Two tile variants per kernel kind, chosen per context by the autotuner
+// (pf_autotune): variant 0 gives each row segment `seg0` contiguous bytes,
+// variant 1 twice that.  Small lines get wider tiles so a work-group has at
+// least one full wavefront; lines shorter than 64 have only variant 0.
+enum ColKind { CK_FFT = 0, CK_STAGE = 1, CK_ELASTIC = 2, CK_FWD_AC = 3, CK_COUNT = 4 };
+static const char* const ck_names[CK_COUNT] = {"colfft", "stage_invz", "zpass_elastic", "zpass_fwd_ac"};
+// The elastic pass holds three fields in registers, so it uses radix-4 ends
+// (half the registers per field) and narrower tiles.
+constexpr int col_re(int kind) { return kind == CK_ELASTIC ? 4 : 8; }
+constexpr int col_tx(int n, int kind, int elem_bytes, int v) {
+  const int seg = (kind == CK_ELASTIC ? 32 : 64) << ((n >= 64) ? v : 0);
+  int tx = seg / elem_bytes;
+  if (tx < 1) tx = 1;
+  while (tx * line_threads(n, col_re(kind)) < 64 && tx < 16) tx *= 2;
+  return tx;
+}
+template <class F>
+static void with_variant(int v, F&& f) {
+  if (v)
+    f(std::integral_constant<int, 1>{});
+  else
+    f(std::integral_constant<int, 0>{});
+}
 // Rows per row-pass work-group: about 256 threads.
 constexpr int rb_of(int m) { return line_threads(m) >= 256 ? 1 : 256 / line_threads(m); }
 
@@ -180,6 +201,10 @@ struct pf_ctx {
   cx<double>* tw64[4] = {nullptr};
   cx<float>* tw32[4] = {nullptr};
 
+  // column-kernel tile variants (see col_tx) and the autotuner's timings
+  int var[CK_COUNT] = {1, 1, 1, 1};
+  double tune_ms[CK_COUNT][2] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
+
   // per-kernel-class HIP-event timing (off by default)
   bool prof_on = false;
   std::vector<hipEvent_t> prof_ev;
@@ -291,53 +316,84 @@ static void setup_model(pf_ctx* c) {
 }
 
 // ---- launchers ----------------------------------------------------------------
+template <typename T, typename TE, int NP>
+static void launch_stage_np(pf_ctx* c, const StageArgs<TE>& sa, cx<T>* out) {
+  const Geo& g = c->g;
+  col_dispatch(g.nz, [&](auto NC) {
+    constexpr int N = decltype(NC)::value;
+    with_variant(c->var[CK_STAGE], [&](auto VC) {
+      constexpr int RE = col_re(CK_STAGE);
+      constexpr int TX = col_tx(N, CK_STAGE, sizeof(cx<T>), decltype(VC)::value);
+      const int nbx = (g.nxh + TX - 1) / TX;
+      k_stage_invz<T, TE, N, TX, RE, NP><<<dim3(nbx * g.ny), dim3(ColGeo<N, TX, RE>::THREADS), 0, c->stream>>>(
+          sa, g, c->mk, tw<T>(c, 0), out);
+    });
+  });
+}
+
 template <typename T, typename TE>
 static bool launch_stage_invz(pf_ctx* c, const StageArgs<TE>& sa, cx<T>* out, int do_fft) {
-  const Geo& g = c->g;
-  constexpr int TX = tx_of<T>();
-  return col_dispatch(g.nz, [&](auto NC) {
-    constexpr int N = decltype(NC)::value;
-    const int nbx = (g.nxh + TX - 1) / TX;
-    k_stage_invz<T, TE, N, TX><<<dim3(nbx * g.ny), dim3(ColGeo<N, TX>::THREADS), 0, c->stream>>>(
-        sa, g, c->mk, tw<T>(c, 0), out, do_fft);
-  });
+  if (!col_supported(c->g.nz)) return false;
+  if (!do_fft) {
+    k_combine<TE><<<dim3(1024), dim3(256), 0, c->stream>>>(sa, c->g, c->mk);
+    return true;
+  }
+  switch (sa.nprev) {
+    case 0: launch_stage_np<T, TE, 0>(c, sa, out); break;
+    case 1: launch_stage_np<T, TE, 1>(c, sa, out); break;
+    case 2: launch_stage_np<T, TE, 2>(c, sa, out); break;
+    case 3: launch_stage_np<T, TE, 3>(c, sa, out); break;
+    case 4: launch_stage_np<T, TE, 4>(c, sa, out); break;
+    case 5: launch_stage_np<T, TE, 5>(c, sa, out); break;
+    default: return false;
+  }
+  return true;
 }
 
 template <typename T, int S, int AXIS>
 static bool launch_colfft(pf_ctx* c, const cx<T>* in, cx<T>* out, int nf, T scale) {
   const Geo& g = c->g;
-  constexpr int TX = tx_of<T>();
   const int n = AXIS == 1 ? g.ny : g.nz;
   const int other = AXIS == 1 ? g.nz : g.ny;
   return col_dispatch(n, [&](auto NC) {
     constexpr int N = decltype(NC)::value;
-    const int nbx = (g.nxh + TX - 1) / TX;
-    k_colfft<T, N, TX, S, AXIS><<<dim3(nbx * other), dim3(ColGeo<N, TX>::THREADS), 0, c->stream>>>(
-        in, out, g, nf, tw<T>(c, AXIS == 1 ? 1 : 0), scale);
+    with_variant(c->var[CK_FFT], [&](auto VC) {
+      constexpr int RE = col_re(CK_FFT);
+      constexpr int TX = col_tx(N, CK_FFT, sizeof(cx<T>), decltype(VC)::value);
+      const int nbx = (g.nxh + TX - 1) / TX;
+      k_colfft<T, N, TX, RE, S, AXIS><<<dim3(nbx * other), dim3(ColGeo<N, TX, RE>::THREADS), 0, c->stream>>>(
+          in, out, g, nf, tw<T>(c, AXIS == 1 ? 1 : 0), scale);
+    });
   });
 }
 
 template <typename T, typename TE>
 static bool launch_zpass_elastic(pf_ctx* c, cx<T>* th, cx<TE>* FEc, int accumulate) {
   const Geo& g = c->g;
-  constexpr int TX = tx_of<T>();
   return col_dispatch(g.nz, [&](auto NC) {
     constexpr int N = decltype(NC)::value;
-    const int nbx = (g.nxh + TX - 1) / TX;
-    k_zpass_elastic<T, TE, N, TX><<<dim3(nbx * g.ny), dim3(ColGeo<N, TX>::THREADS), 0, c->stream>>>(
-        th, g, c->mk, tw<T>(c, 0), FEc, accumulate);
+    with_variant(c->var[CK_ELASTIC], [&](auto VC) {
+      constexpr int RE = col_re(CK_ELASTIC);
+      constexpr int TX = col_tx(N, CK_ELASTIC, sizeof(cx<T>), decltype(VC)::value);
+      const int nbx = (g.nxh + TX - 1) / TX;
+      k_zpass_elastic<T, TE, N, TX, RE><<<dim3(nbx * g.ny), dim3(ColGeo<N, TX, RE>::THREADS), 0, c->stream>>>(
+          th, g, c->mk, tw<T>(c, 0), FEc, accumulate);
+    });
   });
 }
 
 template <typename T, typename TE>
 static bool launch_zpass_fwd_ac(pf_ctx* c, const cx<T>* gk, cx<TE>* FE) {
   const Geo& g = c->g;
-  constexpr int TX = tx_of<T>();
   return col_dispatch(g.nz, [&](auto NC) {
     constexpr int N = decltype(NC)::value;
-    const int nbx = (g.nxh + TX - 1) / TX;
-    k_zpass_fwd_ac<T, TE, N, TX><<<dim3(nbx * g.ny), dim3(ColGeo<N, TX>::THREADS), 0, c->stream>>>(
-        gk, g, c->mk, tw<T>(c, 0), FE);
+    with_variant(c->var[CK_FWD_AC], [&](auto VC) {
+      constexpr int RE = col_re(CK_FWD_AC);
+      constexpr int TX = col_tx(N, CK_FWD_AC, sizeof(cx<T>), decltype(VC)::value);
+      const int nbx = (g.nxh + TX - 1) / TX;
+      k_zpass_fwd_ac<T, TE, N, TX, RE><<<dim3(nbx * g.ny), dim3(ColGeo<N, TX, RE>::THREADS), 0, c->stream>>>(
+          gk, g, c->mk, tw<T>(c, 0), FE);
+    });
   });
 }
 
@@ -957,6 +1013,97 @@ pf_status pf_profile_get(pf_ctx* c, int32_t cls, double* total_ms, int64_t* laun
   if (launches) *launches = c->prof_n[cls];
   if (bytes) *bytes = c->prof_bytes[cls];
   return PF_OK;
+}
+
+}  // extern "C"
+
+// ---- autotuner: time each tile variant of each column kernel on this context
+template <typename T, typename TE>
+static pf_status autotune_impl(pf_ctx* c, int reps) {
+  cx<T>* T1 = (cx<T>*)c->scratch;
+  cx<T>* T3 = T1 + 4 * c->g.fs;
+  int npairs = 0;
+  while (npairs < 3 && c->FI[npairs] && c->FE[npairs]) ++npairs;
+  StageArgs<TE> sa;
+  std::memset(&sa, 0, sizeof(sa));
+  sa.y = c->y;
+  for (int j = 0; j < npairs; ++j) {
+    sa.FE[j] = (const cx<TE>*)c->FE[j];
+    sa.FI[j] = c->FI[j];
+    sa.cE[j] = 1e-3;
+    sa.cI[j] = 1e-3;
+  }
+  sa.nprev = npairs;
+  sa.gdt = 1e-3;
+  sa.FI_out = c->FI[0];
+  hipEvent_t e0, e1;
+  PF_HIP(hipEventCreate(&e0));
+  PF_HIP(hipEventCreate(&e1));
+  for (int k = 0; k < CK_COUNT; ++k) {
+    double best = 1e300;
+    int best_v = 0;
+    for (int v = 0; v < 2; ++v) {
+      c->var[k] = v;
+      auto run = [&]() {
+        switch (k) {
+          case CK_FFT: launch_colfft<T, -1, 1>(c, T1, T1, 4, (T)1); break;
+          case CK_STAGE: launch_stage_invz<T, TE>(c, sa, T1, 1); break;
+          case CK_ELASTIC: launch_zpass_elastic<T, TE>(c, T3, (cx<TE>*)c->FE[0], 0); break;
+          default: launch_zpass_fwd_ac<T, TE>(c, T3, (cx<TE>*)c->FE[0]); break;
+        }
+      };
+      run();
+      PF_HIP(hipEventRecord(e0, c->stream));
+      for (int r = 0; r < reps; ++r) run();
+      PF_HIP(hipEventRecord(e1, c->stream));
+      PF_HIP(hipEventSynchronize(e1));
+      PF_HIP(hipGetLastError());
+      float ms = 0.f;
+      hipEventElapsedTime(&ms, e0, e1);
+      c->tune_ms[k][v] = ms / reps;
+      if (ms < best) {
+        best = ms;
+        best_v = v;
+      }
+    }
+    c->var[k] = best_v;
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  return PF_OK;
+}
+
+extern "C" {
+
+pf_status pf_autotune(pf_ctx* c, int32_t reps) {
+  if (!c || reps < 1) return PF_ERR_ARG;
+  return c->mixed ? autotune_impl<float, float>(c, reps) : autotune_impl<double, double>(c, reps);
+}
+
+int32_t pf_tuning_kinds(void) { return CK_COUNT; }
+
+pf_status pf_tuning_get(pf_ctx* c, int32_t kind, int32_t* variant, int32_t* tile_cols, int32_t* end_radix,
+                        double* ms_v0, double* ms_v1) {
+  if (!c || kind < 0 || kind >= CK_COUNT) return PF_ERR_ARG;
+  const int v = c->var[kind];
+  const int eb = c->mixed ? (int)sizeof(cx<float>) : (int)sizeof(cx<double>);
+  if (variant) *variant = v;
+  if (tile_cols) *tile_cols = col_tx(c->g.nz, kind, eb, v);
+  if (end_radix) *end_radix = col_re(kind);
+  if (ms_v0) *ms_v0 = c->tune_ms[kind][0];
+  if (ms_v1) *ms_v1 = c->tune_ms[kind][1];
+  return PF_OK;
+}
+
+pf_status pf_tuning_set(pf_ctx* c, int32_t kind, int32_t variant) {
+  if (!c || kind < 0 || kind >= CK_COUNT || variant < 0 || variant > 1) return PF_ERR_ARG;
+  c->var[kind] = variant;
+  return PF_OK;
+}
+
+const char* pf_tuning_name(int32_t kind) {
+  if (kind < 0 || kind >= CK_COUNT) return "";
+  return ck_names[kind];
 }
 
 }  // extern "C"

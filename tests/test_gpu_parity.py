@@ -237,3 +237,38 @@ def test_mixed_precision_rhs_error_bound(torch, params, n):
     for f in range(4):
         assert _rel(gI[f], FI[f]) < TOL       # the implicit part stays FP64
         assert errs[f] < 1e-4
+
+
+@pytest.mark.parametrize("shape", [(64, 64, 64), (96, 96, 96), (128, 64, 96)])
+@pytest.mark.parametrize("variant", [0, 1])
+def test_tile_variants_match_oracle(torch, params, shape, variant):
+    """Every column-pass tile variant the autotuner may pick gives the oracle's RHS."""
+    _say("tile variant", variant, shape)
+    c, eta = _rand_fields(shape, seed=3)
+    m = om.Model(shape, params)
+    y = om.to_kspace(c, eta)
+    FI, FE = m.rhs(y)
+    with _solver(shape, params) as s:
+        for k in range(4):
+            s.set_tuning(k, variant)
+        fI, fE = s.rhs(s.kspace_from_numpy(y))
+        gI, gE = s.kspace_to_numpy(fI), s.kspace_to_numpy(fE)
+    for f in range(4):
+        assert _rel(gI[f], FI[f]) < TOL
+        assert _rel(gE[f], FE[f]) < TOL, (f, _rel(gE[f], FE[f]))
+
+
+def test_autotune_then_step_matches_oracle(torch, params):
+    _say("autotune 64^3")
+    n = 64
+    spec, c, eta = pfinputs.config("twin64")
+    m = om.Model((n, n, n), params)
+    y = om.to_kspace(c, eta)
+    with _solver(n, params, method="ark436l", dt0=0.1) as s:
+        s.set_state(c, eta)
+        tun = s.autotune(2)
+        assert set(tun) == {"colfft", "stage_invz", "zpass_elastic", "zpass_fwd_ac"}
+        assert all(v["ms"][0] > 0 and v["ms"][1] > 0 for v in tun.values())
+        s.step(0.1)
+        y1, _, _ = oark.ark_step(y, 0.1, oark.ark436l2sa(), m.f_explicit, m.implicit_symbol())
+        assert _rel(s.kspace_to_numpy(s.get_state_hat()), y1) < TOL
