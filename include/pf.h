@@ -205,6 +205,43 @@ pf_status pf_tuning_get(pf_ctx* ctx, int32_t kind, int32_t* variant, int32_t* ti
                         int32_t* end_radix, double* ms_v0, double* ms_v1);
 pf_status pf_tuning_set(pf_ctx* ctx, int32_t kind, int32_t variant);
 
+/* ---- Batched ensembles (many independent simulations of uneven sizes) ----
+ * n members, each with its own pf_params (cubic grids of 32, 48, 64, 96 or
+ * 128 points; method PF_ARK436L; one precision and one adaptivity setting for
+ * all).  Every pass of the stage cycle is one launch covering all members;
+ * accept / reject and the next step size are decided on the device per
+ * member; one attempted step of all members is captured once as a hipGraph
+ * and replayed.  stream: a hipStream_t or NULL (then the ensemble creates its
+ * own non-blocking stream).  Errors as for pf_init. */
+typedef struct pf_ens pf_ens;
+pf_status pf_ensemble_init(int32_t n, const pf_params* per_member, void* stream, pf_ens** out);
+void pf_ensemble_finalize(pf_ens* ens);
+int32_t pf_ensemble_size_supported(int32_t n);
+int64_t pf_ensemble_workspace_bytes(const pf_ens* ens);
+int64_t pf_ensemble_kspace_pitch(const pf_ens* ens, int32_t member);
+/* Per-member state access, as pf_set_state / pf_get_state / pf_get_state_hat /
+ * pf_diagnostics on member m (0-based); set_state resets the member's time,
+ * step size (dt0) and counters. */
+pf_status pf_ensemble_set_state(pf_ens* ens, int32_t m, const double* c, const double* eta,
+                                int32_t on_device, double t0);
+pf_status pf_ensemble_get_state(pf_ens* ens, int32_t m, double* c, double* eta, int32_t on_device);
+pf_status pf_ensemble_get_state_hat(pf_ens* ens, int32_t m, void* y_hat_device);
+pf_status pf_ensemble_diagnostics(pf_ens* ens, int32_t m, double* mass, double* vf, double* vf_threshold);
+/* Advances every member to its t_final[m] (host array of n values), at most
+ * max_steps attempted steps (graph replays).  Fills per_member[n] if non-NULL.
+ * PF_ERR_STEP_FAIL if a member hit max_rejects consecutive rejections,
+ * PF_ERR_NONFINITE for a non-finite fixed-step member, PF_ERR_STATE if
+ * max_steps ran out first. */
+pf_status pf_ensemble_advance(pf_ens* ens, const double* t_final, int32_t max_steps, pf_stats* per_member);
+/* Autotuner: for each pass kind, time work-groups of 128 and 256 threads on
+ * the whole ensemble and keep the faster (the step graph is re-captured). */
+pf_status pf_ensemble_autotune(pf_ens* ens, int32_t reps);
+int32_t pf_ensemble_tuning_kinds(void);
+const char* pf_ensemble_tuning_name(int32_t kind);
+pf_status pf_ensemble_tuning_get(pf_ens* ens, int32_t kind, int32_t* block_threads, double* ms128,
+                                 double* ms256);
+pf_status pf_ensemble_tuning_set(pf_ens* ens, int32_t kind, int32_t block_threads);
+
 /* Human-readable status name; never NULL. */
 const char* pf_status_string(pf_status s);
 

@@ -14,7 +14,7 @@ import numpy as np
 from . import _lib
 from ._lib import PFError, Stats, make_params  # noqa: F401
 
-__all__ = ["Solver", "PFError", "make_params", "size_supported", "fft3d"]
+__all__ = ["Solver", "Ensemble", "PFError", "make_params", "size_supported"]
 
 
 def _torch():
@@ -201,3 +201,110 @@ class Solver:
     def fft3d(self, direction, nf, src, dst):
         """Standalone 3D real FFT on device tensors (see pf_fft3d)."""
         _lib.check(_lib.lib().pf_fft3d(self._h, int(direction), int(nf), _ptr(src), _ptr(dst)), "pf_fft3d")
+
+
+class Ensemble:
+    """Many independent simulations of uneven cubic sizes advanced together.
+
+    ``members`` is a list of dicts with keys ``n`` (32, 48, 64, 96 or 128) and
+    optionally ``model`` plus any :func:`make_params` keyword (``adaptive``,
+    ``dt0``, ``rtol``, ``atol``, ``precision``; the method is ARK4(3)6L).
+    """
+
+    def __init__(self, members, stream=None):
+        torch = _torch()
+        if not torch.cuda.is_available():
+            raise RuntimeError("libpf needs a GPU (gfx950); none is visible")
+        L = _lib.lib()
+        arr = (_lib.Params * len(members))()
+        self.shapes = []
+        for i, mb in enumerate(members):
+            kw = {k: v for k, v in mb.items() if k not in ("n", "model")}
+            kw.setdefault("method", "ark436l")
+            arr[i] = make_params(int(mb["n"]), mb.get("model"), **kw)
+            self.shapes.append((arr[i].nz, arr[i].ny, arr[i].nx))
+        self.M = len(members)
+        h = ctypes.c_void_p()
+        sp = ctypes.c_void_p(stream.cuda_stream) if stream is not None else ctypes.c_void_p(0)
+        _lib.check(L.pf_ensemble_init(self.M, arr, sp, ctypes.byref(h)), "pf_ensemble_init")
+        self._h = h
+        self._params = arr
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.lib().pf_ensemble_finalize(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    @property
+    def workspace_bytes(self):
+        return int(_lib.lib().pf_ensemble_workspace_bytes(self._h))
+
+    def set_state(self, m, c, eta, t0=0.0):
+        c = np.ascontiguousarray(c, dtype=np.float64)
+        eta = np.ascontiguousarray(eta, dtype=np.float64)
+        assert c.shape == self.shapes[m] and eta.shape == (3,) + self.shapes[m]
+        _lib.check(_lib.lib().pf_ensemble_set_state(self._h, int(m), c.ctypes.data_as(ctypes.c_void_p),
+                                                    eta.ctypes.data_as(ctypes.c_void_p), 0, float(t0)),
+                   "pf_ensemble_set_state")
+
+    def get_state(self, m):
+        c = np.empty(self.shapes[m])
+        eta = np.empty((3,) + self.shapes[m])
+        _lib.check(_lib.lib().pf_ensemble_get_state(self._h, int(m), c.ctypes.data_as(ctypes.c_void_p),
+                                                    eta.ctypes.data_as(ctypes.c_void_p), 0),
+                   "pf_ensemble_get_state")
+        return c, eta
+
+    def get_state_hat(self, m):
+        """Member m's reciprocal-space state as a numpy array (4, nz, ny, nx//2+1)."""
+        torch = _torch()
+        nz, ny, nx = self.shapes[m]
+        kp = int(_lib.lib().pf_ensemble_kspace_pitch(self._h, int(m)))
+        t = torch.empty((4, nz, ny, kp), dtype=torch.complex128, device="cuda")
+        _lib.check(_lib.lib().pf_ensemble_get_state_hat(self._h, int(m), _ptr(t)), "pf_ensemble_get_state_hat")
+        return t[..., : nx // 2 + 1].cpu().numpy()
+
+    def diagnostics(self, m):
+        a, b, c = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        _lib.check(_lib.lib().pf_ensemble_diagnostics(self._h, int(m), ctypes.byref(a), ctypes.byref(b),
+                                                      ctypes.byref(c)), "pf_ensemble_diagnostics")
+        return dict(mass=a.value, vf=b.value, vf_threshold=c.value)
+
+    def advance(self, t_final, max_steps=100000):
+        """Advance every member to t_final (scalar or per member); returns per-member stats."""
+        tf = np.broadcast_to(np.asarray(t_final, dtype=np.float64), (self.M,)).copy()
+        st = (Stats * self.M)()
+        code = _lib.lib().pf_ensemble_advance(self._h, tf.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                              int(min(max_steps, 2**31 - 1)), st)
+        _lib.check(code, "pf_ensemble_advance")
+        return [st[i].as_dict() for i in range(self.M)]
+
+    def autotune(self, reps=3):
+        _lib.check(_lib.lib().pf_ensemble_autotune(self._h, int(reps)), "pf_ensemble_autotune")
+        return self.tuning()
+
+    def tuning(self):
+        L = _lib.lib()
+        out = {}
+        for k in range(L.pf_ensemble_tuning_kinds()):
+            bt, a, b = ctypes.c_int32(), ctypes.c_double(), ctypes.c_double()
+            _lib.check(L.pf_ensemble_tuning_get(self._h, k, ctypes.byref(bt), ctypes.byref(a), ctypes.byref(b)),
+                       "pf_ensemble_tuning_get")
+            out[L.pf_ensemble_tuning_name(k).decode()] = dict(block_threads=bt.value, ms=[a.value, b.value])
+        return out
+
+    def set_tuning(self, kind, block_threads):
+        _lib.check(_lib.lib().pf_ensemble_tuning_set(self._h, int(kind), int(block_threads)),
+                   "pf_ensemble_tuning_set")

@@ -91,6 +91,27 @@ _SIGS = {
                                      ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                                      ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
     "pf_tuning_set": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32]),
+    "pf_ensemble_init": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(Params), ctypes.c_void_p,
+                                        ctypes.POINTER(ctypes.c_void_p)]),
+    "pf_ensemble_finalize": (None, [ctypes.c_void_p]),
+    "pf_ensemble_size_supported": (ctypes.c_int32, [ctypes.c_int32]),
+    "pf_ensemble_workspace_bytes": (ctypes.c_int64, [ctypes.c_void_p]),
+    "pf_ensemble_kspace_pitch": (ctypes.c_int64, [ctypes.c_void_p, ctypes.c_int32]),
+    "pf_ensemble_set_state": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                                             ctypes.c_int32, ctypes.c_double]),
+    "pf_ensemble_get_state": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                                             ctypes.c_int32]),
+    "pf_ensemble_get_state_hat": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
+    "pf_ensemble_diagnostics": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
+                                               ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
+    "pf_ensemble_advance": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_int32,
+                                           ctypes.POINTER(Stats)]),
+    "pf_ensemble_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
+    "pf_ensemble_tuning_kinds": (ctypes.c_int32, []),
+    "pf_ensemble_tuning_name": (ctypes.c_char_p, [ctypes.c_int32]),
+    "pf_ensemble_tuning_get": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                              ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
+    "pf_ensemble_tuning_set": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32]),
     "pf_profile_enable": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "pf_profile_classes": (ctypes.c_int32, []),
     "pf_profile_name": (ctypes.c_char_p, [ctypes.c_int32]),

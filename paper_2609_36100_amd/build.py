@@ -7,11 +7,12 @@ import sys
 import time
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRC = os.path.join(HERE, "csrc", "pf_runtime.hip")
+SRCS = [os.path.join(HERE, "csrc", f) for f in ("pf_runtime.hip", "pf_ensemble.hip")]
 OUT = os.path.join(HERE, "libpf.so")
+OBJDIR = os.path.join(HERE, "_build")
 
 HIPCC_FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     # keep hipcc from emitting packed FP32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-result",
@@ -19,14 +20,31 @@ HIPCC_FLAGS = [
 
 
 def build(verbose=True):
+    """Compile every translation unit in parallel, then link libpf.so."""
     hipcc = os.environ.get("HIPCC", "hipcc")
-    tmp = OUT + ".tmp"
-    cmd = [hipcc, *HIPCC_FLAGS, "-o", tmp, SRC]
+    os.makedirs(OBJDIR, exist_ok=True)
     t0 = time.time()
-    r = subprocess.run(cmd, capture_output=True, text=True)
+    procs = []
+    objs = []
+    for src in SRCS:
+        obj = os.path.join(OBJDIR, os.path.basename(src) + ".o")
+        objs.append(obj)
+        procs.append((src, subprocess.Popen([hipcc, *HIPCC_FLAGS, "-c", "-o", obj, src],
+                                            stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True)))
+    failed = False
+    for src, p in procs:
+        out, err = p.communicate()
+        if p.returncode != 0:
+            sys.stderr.write(err)
+            failed = True
+    if failed:
+        raise RuntimeError("hipcc failed")
+    tmp = OUT + ".tmp"
+    r = subprocess.run([hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs],
+                       capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stderr)
-        raise RuntimeError("hipcc failed (%d)" % r.returncode)
+        raise RuntimeError("link failed (%d)" % r.returncode)
     os.replace(tmp, OUT)
     if verbose:
         print("built %s in %.1fs" % (OUT, time.time() - t0), flush=True)

@@ -1,0 +1,159 @@
+// libpf context: the per-simulation state shared by the runtime translation
+// units (single-grid runtime and the batched ensemble).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+#include <utility>
+#include <vector>
+
+#include "../../include/pf.h"
+#include "pf_kernels.hpp"
+
+namespace pf {
+
+enum ColKind { CK_FFT = 0, CK_STAGE = 1, CK_ELASTIC = 2, CK_FWD_AC = 3, CK_COUNT = 4 };
+
+// ---- ImEx-ARK tables ---------------------------------------------------------
+struct ArkTable {
+  int s;
+  int order, emb_order;
+  int has_emb;
+  double AE[6][6], AI[6][6], bE[6], bI[6], bt[6];
+};
+
+inline ArkTable table_imex_euler() {
+  ArkTable t;
+  std::memset(&t, 0, sizeof(t));
+  t.s = 2;
+  t.order = 1;
+  t.AE[1][0] = 1.0;
+  t.AI[1][1] = 1.0;
+  t.bE[0] = 1.0;
+  t.bI[1] = 1.0;
+  return t;
+}
+
+// ARK4(3)6L[2]SA (Kennedy & Carpenter 2003): published rational coefficients.
+inline ArkTable table_ark436l() {
+  ArkTable t;
+  std::memset(&t, 0, sizeof(t));
+  t.s = 6;
+  t.order = 4;
+  t.emb_order = 3;
+  t.has_emb = 1;
+  double(*E)[6] = t.AE;
+  E[1][0] = 1.0 / 2.0;
+  E[2][0] = 13861.0 / 62500.0;
+  E[2][1] = 6889.0 / 62500.0;
+  E[3][0] = -116923316275.0 / 2393684061468.0;
+  E[3][1] = -2731218467317.0 / 15368042101831.0;
+  E[3][2] = 9408046702089.0 / 11113171139209.0;
+  E[4][0] = -451086348788.0 / 2902428689909.0;
+  E[4][1] = -2682348792572.0 / 7519795681897.0;
+  E[4][2] = 12662868775082.0 / 11960479115383.0;
+  E[4][3] = 3355817975965.0 / 11060851509271.0;
+  E[5][0] = 647845179188.0 / 3216320057751.0;
+  E[5][1] = 73281519250.0 / 8382639484533.0;
+  E[5][2] = 552539513391.0 / 3454668386233.0;
+  E[5][3] = 3354512671639.0 / 8306763924573.0;
+  E[5][4] = 4040.0 / 17871.0;
+  const double b[6] = {82889.0 / 524892.0, 0.0, 15625.0 / 83664.0, 69875.0 / 102672.0,
+                       -2260.0 / 8211.0, 1.0 / 4.0};
+  const double bt[6] = {4586570599.0 / 29645900160.0, 0.0, 178811875.0 / 945068544.0,
+                        814220225.0 / 1159782912.0, -3700637.0 / 11593932.0, 61727.0 / 225920.0};
+  double(*I)[6] = t.AI;
+  const double g = 1.0 / 4.0;
+  I[1][0] = g;
+  I[1][1] = g;
+  I[2][0] = 8611.0 / 62500.0;
+  I[2][1] = -1743.0 / 31250.0;
+  I[2][2] = g;
+  I[3][0] = 5012029.0 / 34652500.0;
+  I[3][1] = -654441.0 / 2922500.0;
+  I[3][2] = 174375.0 / 388108.0;
+  I[3][3] = g;
+  I[4][0] = 15267082809.0 / 155376265600.0;
+  I[4][1] = -71443401.0 / 120774400.0;
+  I[4][2] = 730878875.0 / 902184768.0;
+  I[4][3] = 2285395.0 / 8070912.0;
+  I[4][4] = g;
+  for (int j = 0; j < 6; ++j) {
+    I[5][j] = b[j];
+    t.bE[j] = b[j];
+    t.bI[j] = b[j];
+    t.bt[j] = bt[j];
+  }
+  return t;
+}
+
+inline bool fe_needed(const ArkTable& t, int i) {
+  if (t.bE[i] != 0.0 || (t.has_emb && t.bt[i] != 0.0)) return true;
+  for (int k = i + 1; k < t.s; ++k)
+    if (t.AE[k][i] != 0.0) return true;
+  return false;
+}
+inline bool fi_needed(const ArkTable& t, int i) {
+  if (t.bI[i] != 0.0 || (t.has_emb && t.bI[i] - t.bt[i] != 0.0)) return true;
+  for (int k = i + 1; k < t.s; ++k)
+    if (t.AI[k][i] != 0.0) return true;
+  return false;
+}
+
+// ---- context -----------------------------------------------------------------
+}  // namespace pf
+
+struct pf_ctx {
+  pf_params p;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  pf::Geo g;
+  pf::ModelK mk;
+  pf::ArkTable tab;
+  bool fe_need[6], fi_need[6];
+  int mixed = 0;
+
+  bool owns = true;  // false for views whose buffers belong to an ensemble
+  pf::cx<double>* y = nullptr;
+  pf::cx<double>* ynew = nullptr;
+  pf::cx<double>* FI[6] = {nullptr};
+  void* FE[6] = {nullptr};  // cx<double> (FP64) or cx<float> (mixed)
+  void* scratch = nullptr;  // T1 (4 fields) | T3 (3 fields) of the FFT precision
+  size_t scratch_bytes = 0;
+  double* partial = nullptr;
+  double* red = nullptr;
+  double* host_red = nullptr;  // pinned
+  int nblk_red = 1024;
+
+  // twiddle tables: 0 = z (N_z), 1 = y (N_y), 2 = x half length (M), 3 = x real length (N_x)
+  pf::cx<double>* tw64[4] = {nullptr};
+  pf::cx<float>* tw32[4] = {nullptr};
+
+  // column-kernel tile variants (see col_tx) and the autotuner's timings
+  int var[pf::CK_COUNT] = {1, 1, 1, 1};
+  double tune_ms[pf::CK_COUNT][2] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
+
+  // per-kernel-class HIP-event timing (off by default)
+  bool prof_on = false;
+  std::vector<hipEvent_t> prof_ev;
+  size_t prof_used = 0;
+  std::vector<std::pair<int, double>> prof_pending;  // (class, algorithmic bytes)
+  double prof_ms[16] = {0}, prof_bytes[16] = {0};
+  int64_t prof_n[16] = {0};
+
+  int64_t ws_bytes = 0;
+  double t = 0.0;
+  double dt_next = 0.0;
+  bool have_state = false;
+  pf_stats st;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+};
+
+
+namespace pf {
+// Shared by the runtime translation units (defined in pf_runtime.hip).
+void ctx_setup(pf_ctx* c, const pf_params* p, hipStream_t stream);   // geometry, model, tables
+void make_twiddles64(int n, cx<double>* host);
+void make_twiddles32(int n, cx<float>* host);
+}  // namespace pf

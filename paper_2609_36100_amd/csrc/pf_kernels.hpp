@@ -140,7 +140,7 @@ __host__ __device__ constexpr int plan_prod(int n, int q, int re) {
 template <typename T, int N, int S, int Q, int RE>
 struct MidPass {
   template <class Buf>
-  __device__ static inline void run(int tid, const cx<T>* tw, Buf buf) {
+  __device__ static inline void run(int tid, const cx<T>* tw, Buf buf, bool act) {
     constexpr Plan PL = plan(N, RE);
     if constexpr (Q < PL.np - 1) {
       constexpr int r = PL.r[Q];
@@ -152,7 +152,7 @@ struct MidPass {
 #pragma unroll
       for (int j = 0; j < PER; ++j) {
         const int b = tid + j * TL;
-        if (PER * TL == NB || b < NB) {
+        if (act && (PER * TL == NB || b < NB)) {
           const int k = b % p;
 #pragma unroll
           for (int t = 0; t < r; ++t) v[j][t] = buf(b + t * NB);
@@ -165,14 +165,14 @@ struct MidPass {
 #pragma unroll
       for (int j = 0; j < PER; ++j) {
         const int b = tid + j * TL;
-        if (PER * TL == NB || b < NB) {
+        if (act && (PER * TL == NB || b < NB)) {
           const int k = b % p;
 #pragma unroll
           for (int t = 0; t < r; ++t) buf((b - k) * r + k + t * p) = v[j][t];
         }
       }
       __syncthreads();
-      MidPass<T, N, S, Q + 1, RE>::run(tid, tw, buf);
+      MidPass<T, N, S, Q + 1, RE>::run(tid, tw, buf, act);
     }
   }
 };
@@ -181,9 +181,11 @@ struct MidPass {
 // (r0 = the plan's end radix, at most RE).  On entry a[t] holds
 // x[tid + t N/r0]; on exit X[tid + t N/r0].  Every thread of the work-group
 // must call this the same number of times (it contains work-group barriers);
-// the LDS region behind `buf` must hold N values.
+// the LDS region behind `buf` must hold N values.  Threads with act = false
+// only take part in the barriers (work-groups shared by lines of different
+// lengths have idle threads).
 template <typename T, int N, int S, int RE = 8, class Buf>
-__device__ inline void line_fft(cx<T>* a, int tid, const cx<T>* tw, Buf buf) {
+__device__ inline void line_fft(cx<T>* a, int tid, const cx<T>* tw, Buf buf, bool act = true) {
   constexpr Plan PL = plan(N, RE);
   static_assert(PL.ok, "unsupported line length");
   constexpr int R0 = PL.r[0];
@@ -191,12 +193,16 @@ __device__ inline void line_fft(cx<T>* a, int tid, const cx<T>* tw, Buf buf) {
   dft<R0, S>(a);
   if constexpr (PL.np > 1) {
     __syncthreads();
+    if (act) {
 #pragma unroll
-    for (int t = 0; t < R0; ++t) buf(tid * R0 + t) = a[t];
+      for (int t = 0; t < R0; ++t) buf(tid * R0 + t) = a[t];
+    }
     __syncthreads();
-    MidPass<T, N, S, 1, RE>::run(tid, tw, buf);
+    MidPass<T, N, S, 1, RE>::run(tid, tw, buf, act);
+    if (act) {
 #pragma unroll
-    for (int t = 0; t < R0; ++t) a[t] = buf(tid + t * TL);
+      for (int t = 0; t < R0; ++t) a[t] = buf(tid + t * TL);
+    }
     // last pass: p = N / R0, k = tid, twiddle w_N^{t tid}
     apply_twiddles<R0, S>(a, tw, tid);
     dft<R0, S>(a);
@@ -262,19 +268,18 @@ __device__ inline cx<double> stage_value(const StageArgs<TE>& sa, long long idx,
   return zz;
 }
 
-template <typename T, typename TE, int N, int TX, int RE, int NP>
-__global__ void __launch_bounds__((ColGeo<N, TX, RE>::THREADS))
-k_stage_invz(StageArgs<TE> sa, Geo g, ModelK m, const cx<T>* twz, cx<T>* __restrict__ out) {
+template <typename T, typename TE, int N, int TX, int RE, int NP, bool GUARD = false>
+__device__ inline void body_stage_invz(const StageArgs<TE>& sa, const Geo& g, const ModelK& m, const cx<T>* twz,
+                                       cx<T>* out, int tile, int tid, cx<T>* lds) {
   using CG = ColGeo<N, TX, RE>;
-  __shared__ cx<T> lds[N * CG::LD];
+  const bool act = !GUARD || tid < CG::THREADS;
   const int nbx = (g.nxh + TX - 1) / TX;
-  const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int xb = tile % nbx;
   const int y = tile / nbx;
-  const int col = threadIdx.x % TX;
-  const int bf = threadIdx.x / TX;
+  const int col = tid % TX;
+  const int bf = tid / TX;
   const int x = xb * TX + col;
-  const bool valid = x < g.nxh;
+  const bool valid = act && x < g.nxh;
   const double kx = x * g.kfx;
   const double ky = mode_of(y, g.ny) * g.kfy;
   auto buf = [&](int pos) -> cx<T>& { return lds[pos * CG::LD + col]; };
@@ -292,13 +297,13 @@ k_stage_invz(StageArgs<TE> sa, Geo g, ModelK m, const cx<T>* twz, cx<T>* __restr
         const double k2 = kx * kx + ky * ky + kz * kz;
         r = m.inv_n3 * stage_value<TE, NP>(sa, idx, lsym(m, f, k2), sa.FI_out, sa.FEc_out, m.fEa * k2, f);
       }
-      buf(z) = to_t<T>(r);
+      if (act) buf(z) = to_t<T>(r);
     }
     __syncthreads();
     cx<T> a[CG::R0];
 #pragma unroll
-    for (int t = 0; t < CG::R0; ++t) a[t] = buf(bf + t * CG::TL);
-    line_fft<T, N, +1, RE>(a, bf, twz, buf);
+    for (int t = 0; t < CG::R0; ++t) a[t] = act ? buf(bf + t * CG::TL) : mk<T>(0, 0);
+    line_fft<T, N, +1, RE>(a, bf, twz, buf, act);
     if (valid) {
 #pragma unroll
       for (int t = 0; t < CG::R0; ++t) {
@@ -307,6 +312,13 @@ k_stage_invz(StageArgs<TE> sa, Geo g, ModelK m, const cx<T>* twz, cx<T>* __restr
       }
     }
   }
+}
+
+template <typename T, typename TE, int N, int TX, int RE, int NP>
+__global__ void __launch_bounds__((ColGeo<N, TX, RE>::THREADS))
+k_stage_invz(StageArgs<TE> sa, Geo g, ModelK m, const cx<T>* twz, cx<T>* __restrict__ out) {
+  __shared__ cx<T> lds[N * ColGeo<N, TX, RE>::LD];
+  body_stage_invz<T, TE, N, TX, RE, NP>(sa, g, m, twz, out, xcd_tile(blockIdx.x, gridDim.x), threadIdx.x, lds);
 }
 
 // Stage combination and implicit solve only (a stage whose explicit
@@ -338,19 +350,18 @@ __global__ void __launch_bounds__(256) k_combine(StageArgs<TE> sa, Geo g, ModelK
 
 // ---- generic column FFT along y or z (in or out of place) -----------------
 // axis 1 = y (lines at fixed z), axis 2 = z (lines at fixed y).
-template <typename T, int N, int TX, int RE, int S, int AXIS>
-__global__ void __launch_bounds__((ColGeo<N, TX, RE>::THREADS))
-k_colfft(const cx<T>* in, cx<T>* out, Geo g, int nf, const cx<T>* tw, T scale) {
+template <typename T, int N, int TX, int RE, int S, int AXIS, bool GUARD = false>
+__device__ inline void body_colfft(const cx<T>* in, cx<T>* out, const Geo& g, int nf, const cx<T>* tw, T scale,
+                                   int tile, int tid, cx<T>* lds) {
   using CG = ColGeo<N, TX, RE>;
-  __shared__ cx<T> lds[N * CG::LD];
+  const bool act = !GUARD || tid < CG::THREADS;
   const int nbx = (g.nxh + TX - 1) / TX;
-  const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int xb = tile % nbx;
   const int o = tile / nbx;  // fixed z (AXIS 1) or fixed y (AXIS 2)
-  const int col = threadIdx.x % TX;
-  const int bf = threadIdx.x / TX;
+  const int col = tid % TX;
+  const int bf = tid / TX;
   const int x = xb * TX + col;
-  const bool valid = x < g.nxh;
+  const bool valid = act && x < g.nxh;
   const long long lstride = AXIS == 1 ? (long long)g.P : (long long)g.ny * g.P;
   const long long base = AXIS == 1 ? (long long)o * g.ny * g.P + x : (long long)o * g.P + x;
   auto buf = [&](int pos) -> cx<T>& { return lds[pos * CG::LD + col]; };
@@ -362,7 +373,7 @@ k_colfft(const cx<T>* in, cx<T>* out, Geo g, int nf, const cx<T>* tw, T scale) {
       const int q = bf + t * CG::TL;
       a[t] = valid ? in[fb + q * lstride] : mk<T>(0, 0);
     }
-    line_fft<T, N, S, RE>(a, bf, tw, buf);
+    line_fft<T, N, S, RE>(a, bf, tw, buf, act);
     if (valid) {
 #pragma unroll
       for (int t = 0; t < CG::R0; ++t) {
@@ -373,21 +384,26 @@ k_colfft(const cx<T>* in, cx<T>* out, Geo g, int nf, const cx<T>* tw, T scale) {
   }
 }
 
-// ---- K-E: forward z-FFT of theta, elastic solve, explicit CH, inverse z ----
-template <typename T, typename TE, int N, int TX, int RE>
+template <typename T, int N, int TX, int RE, int S, int AXIS>
 __global__ void __launch_bounds__((ColGeo<N, TX, RE>::THREADS))
-k_zpass_elastic(cx<T>* __restrict__ th, Geo g, ModelK m, const cx<T>* twz,
-                cx<TE>* __restrict__ FEc, int accumulate) {
+k_colfft(const cx<T>* in, cx<T>* out, Geo g, int nf, const cx<T>* tw, T scale) {
+  __shared__ cx<T> lds[N * ColGeo<N, TX, RE>::LD];
+  body_colfft<T, N, TX, RE, S, AXIS>(in, out, g, nf, tw, scale, xcd_tile(blockIdx.x, gridDim.x), threadIdx.x, lds);
+}
+
+// ---- K-E: forward z-FFT of theta, elastic solve, explicit CH, inverse z ----
+template <typename T, typename TE, int N, int TX, int RE, bool GUARD = false>
+__device__ inline void body_zpass_elastic(cx<T>* th, const Geo& g, const ModelK& m, const cx<T>* twz, cx<TE>* FEc,
+                                          int accumulate, int tile, int tid, cx<T>* lds) {
   using CG = ColGeo<N, TX, RE>;
-  __shared__ cx<T> lds[N * CG::LD];
+  const bool act = !GUARD || tid < CG::THREADS;
   const int nbx = (g.nxh + TX - 1) / TX;
-  const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int xb = tile % nbx;
   const int y = tile / nbx;
-  const int col = threadIdx.x % TX;
-  const int bf = threadIdx.x / TX;
+  const int col = tid % TX;
+  const int bf = tid / TX;
   const int x = xb * TX + col;
-  const bool valid = x < g.nxh;
+  const bool valid = act && x < g.nxh;
   const long long lstride = (long long)g.ny * g.P;
   const long long base = (long long)y * g.P + x;
   auto buf = [&](int pos) -> cx<T>& { return lds[pos * CG::LD + col]; };
@@ -399,7 +415,7 @@ k_zpass_elastic(cx<T>* __restrict__ th, Geo g, ModelK m, const cx<T>* twz,
       const int z = bf + t * CG::TL;
       a[v][t] = valid ? th[v * g.fs + base + z * lstride] : mk<T>(0, 0);
     }
-    line_fft<T, N, -1, RE>(a[v], bf, twz, buf);
+    line_fft<T, N, -1, RE>(a[v], bf, twz, buf, act);
   }
   const T kx = (T)(x * g.kfx);
   const T ky = (T)(mode_of(y, g.ny) * g.kfy);
@@ -441,7 +457,7 @@ k_zpass_elastic(cx<T>* __restrict__ th, Geo g, ModelK m, const cx<T>* twz,
   }
 #pragma unroll
   for (int v = 0; v < 3; ++v) {
-    line_fft<T, N, +1, RE>(a[v], bf, twz, buf);
+    line_fft<T, N, +1, RE>(a[v], bf, twz, buf, act);
     if (valid) {
 #pragma unroll
       for (int t = 0; t < CG::R0; ++t) {
@@ -452,21 +468,28 @@ k_zpass_elastic(cx<T>* __restrict__ th, Geo g, ModelK m, const cx<T>* twz,
   }
 }
 
-// ---- K-I: forward z-FFT of the AC driving force, F^E_eta = -L g~ ----------
 template <typename T, typename TE, int N, int TX, int RE>
 __global__ void __launch_bounds__((ColGeo<N, TX, RE>::THREADS))
-k_zpass_fwd_ac(const cx<T>* __restrict__ gk, Geo g, ModelK m, const cx<T>* twz,
-               cx<TE>* __restrict__ FE) {
+k_zpass_elastic(cx<T>* __restrict__ th, Geo g, ModelK m, const cx<T>* twz, cx<TE>* __restrict__ FEc,
+                int accumulate) {
+  __shared__ cx<T> lds[N * ColGeo<N, TX, RE>::LD];
+  body_zpass_elastic<T, TE, N, TX, RE>(th, g, m, twz, FEc, accumulate, xcd_tile(blockIdx.x, gridDim.x),
+                                       threadIdx.x, lds);
+}
+
+// ---- K-I: forward z-FFT of the AC driving force, F^E_eta = -L g~ ----------
+template <typename T, typename TE, int N, int TX, int RE, bool GUARD = false>
+__device__ inline void body_zpass_fwd_ac(const cx<T>* gk, const Geo& g, const ModelK& m, const cx<T>* twz,
+                                         cx<TE>* FE, int tile, int tid, cx<T>* lds) {
   using CG = ColGeo<N, TX, RE>;
-  __shared__ cx<T> lds[N * CG::LD];
+  const bool act = !GUARD || tid < CG::THREADS;
   const int nbx = (g.nxh + TX - 1) / TX;
-  const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int xb = tile % nbx;
   const int y = tile / nbx;
-  const int col = threadIdx.x % TX;
-  const int bf = threadIdx.x / TX;
+  const int col = tid % TX;
+  const int bf = tid / TX;
   const int x = xb * TX + col;
-  const bool valid = x < g.nxh;
+  const bool valid = act && x < g.nxh;
   const long long lstride = (long long)g.ny * g.P;
   const long long base = (long long)y * g.P + x;
   auto buf = [&](int pos) -> cx<T>& { return lds[pos * CG::LD + col]; };
@@ -478,7 +501,7 @@ k_zpass_fwd_ac(const cx<T>* __restrict__ gk, Geo g, ModelK m, const cx<T>* twz,
       const int z = bf + t * CG::TL;
       a[t] = valid ? gk[v * g.fs + base + z * lstride] : mk<T>(0, 0);
     }
-    line_fft<T, N, -1, RE>(a, bf, twz, buf);
+    line_fft<T, N, -1, RE>(a, bf, twz, buf, act);
     if (valid) {
 #pragma unroll
       for (int t = 0; t < CG::R0; ++t) {
@@ -488,6 +511,13 @@ k_zpass_fwd_ac(const cx<T>* __restrict__ gk, Geo g, ModelK m, const cx<T>* twz,
       }
     }
   }
+}
+
+template <typename T, typename TE, int N, int TX, int RE>
+__global__ void __launch_bounds__((ColGeo<N, TX, RE>::THREADS))
+k_zpass_fwd_ac(const cx<T>* __restrict__ gk, Geo g, ModelK m, const cx<T>* twz, cx<TE>* __restrict__ FE) {
+  __shared__ cx<T> lds[N * ColGeo<N, TX, RE>::LD];
+  body_zpass_fwd_ac<T, TE, N, TX, RE>(gk, g, m, twz, FE, xcd_tile(blockIdx.x, gridDim.x), threadIdx.x, lds);
 }
 
 // ---- row (x-axis) passes ---------------------------------------------------
@@ -503,41 +533,47 @@ struct RowGeo {
 // n = bf + t TL.  Unnormalised (full-spectrum sum).
 template <typename T, int M, int RB>
 __device__ inline void row_c2r(const cx<T>* src, bool rvalid, cx<T>* a, int bf, cx<T>* rbuf,
-                               const cx<T>* twN, const cx<T>* twM) {
+                               const cx<T>* twN, const cx<T>* twM, bool act = true) {
   using RG = RowGeo<M, RB>;
   __syncthreads();
+  if (act) {
 #pragma unroll
-  for (int t = 0; t < RG::R0; ++t) {
-    const int k = bf + t * RG::TL;
-    rbuf[k] = rvalid ? src[k] : mk<T>(0, 0);
-  }
-  if (bf == 0) rbuf[M] = rvalid ? src[M] : mk<T>(0, 0);
-  __syncthreads();
-#pragma unroll
-  for (int t = 0; t < RG::R0; ++t) {
-    const int k = bf + t * RG::TL;
-    cx<T> xk = rbuf[k];
-    cx<T> xmk = rbuf[M - k];
-    if (k == 0) {
-      xk.im = (T)0;
-      xmk.im = (T)0;
+    for (int t = 0; t < RG::R0; ++t) {
+      const int k = bf + t * RG::TL;
+      rbuf[k] = rvalid ? src[k] : mk<T>(0, 0);
     }
-    a[t] = c2r_pre(xk, xmk, twN[k]);
+    if (bf == 0) rbuf[M] = rvalid ? src[M] : mk<T>(0, 0);
   }
-  line_fft<T, M, +1>(a, bf, twM, [&](int pos) -> cx<T>& { return rbuf[pos]; });
+  __syncthreads();
+  if (act) {
+#pragma unroll
+    for (int t = 0; t < RG::R0; ++t) {
+      const int k = bf + t * RG::TL;
+      cx<T> xk = rbuf[k];
+      cx<T> xmk = rbuf[M - k];
+      if (k == 0) {
+        xk.im = (T)0;
+        xmk.im = (T)0;
+      }
+      a[t] = c2r_pre(xk, xmk, twN[k]);
+    }
+  }
+  line_fft<T, M, +1>(a, bf, twM, [&](int pos) -> cx<T>& { return rbuf[pos]; }, act);
 }
 
 // r2c of real pairs a[t] (n = bf + t TL) into half-spectrum row dst[0..M].
 template <typename T, int M, int RB>
 __device__ inline void row_r2c(cx<T>* a, cx<T>* dst, bool rvalid, int bf, cx<T>* rbuf,
-                               const cx<T>* twN, const cx<T>* twM) {
+                               const cx<T>* twN, const cx<T>* twM, bool act = true) {
   using RG = RowGeo<M, RB>;
-  line_fft<T, M, -1>(a, bf, twM, [&](int pos) -> cx<T>& { return rbuf[pos]; });
+  line_fft<T, M, -1>(a, bf, twM, [&](int pos) -> cx<T>& { return rbuf[pos]; }, act);
   __syncthreads();
+  if (act) {
 #pragma unroll
-  for (int t = 0; t < RG::R0; ++t) rbuf[bf + t * RG::TL] = a[t];
+    for (int t = 0; t < RG::R0; ++t) rbuf[bf + t * RG::TL] = a[t];
+  }
   __syncthreads();
-  if (rvalid) {
+  if (act && rvalid) {
 #pragma unroll
     for (int t = 0; t < RG::R0; ++t) {
       const int k = bf + t * RG::TL;
@@ -561,45 +597,51 @@ __device__ inline T dhfun(T e) {
 }
 
 // K-C: theta_v = h(eta_v) (rows of the 3 eta fields of `st` -> rows of `th`).
-template <typename T, int M, int RB>
-__global__ void __launch_bounds__((RowGeo<M, RB>::THREADS))
-k_xpass_theta(const cx<T>* __restrict__ st, cx<T>* __restrict__ th, Geo g,
-              const cx<T>* twN, const cx<T>* twM) {
+template <typename T, int M, int RB, bool GUARD = false>
+__device__ inline void body_xpass_theta(const cx<T>* st, cx<T>* th, const Geo& g, const cx<T>* twN,
+                                        const cx<T>* twM, int tile, int tid, cx<T>* lds) {
   using RG = RowGeo<M, RB>;
-  __shared__ cx<T> lds[RB * RG::LD];
-  const int rl = threadIdx.x / RG::TL;
-  const int bf = threadIdx.x % RG::TL;
-  const int row = blockIdx.x * RB + rl;
-  const bool rvalid = row < g.nz * g.ny;
-  cx<T>* rbuf = lds + rl * RG::LD;
+  const bool act = !GUARD || tid < RG::THREADS;
+  const int rl = tid / RG::TL;
+  const int bf = tid % RG::TL;
+  const int row = tile * RB + rl;
+  const bool rvalid = act && row < g.nz * g.ny;
+  cx<T>* rbuf = lds + (act ? rl : 0) * RG::LD;
   const long long rb = (long long)(rvalid ? row : 0) * g.P;
   for (int v = 0; v < 3; ++v) {
     cx<T> a[RG::R0];
-    row_c2r<T, M, RB>(st + (1 + v) * g.fs + rb, rvalid, a, bf, rbuf, twN, twM);
+    row_c2r<T, M, RB>(st + (1 + v) * g.fs + rb, rvalid, a, bf, rbuf, twN, twM, act);
 #pragma unroll
     for (int t = 0; t < RG::R0; ++t) a[t] = mk<T>(hfun(a[t].re), hfun(a[t].im));
-    row_r2c<T, M, RB>(a, th + v * g.fs + rb, rvalid, bf, rbuf, twN, twM);
+    row_r2c<T, M, RB>(a, th + v * g.fs + rb, rvalid, bf, rbuf, twN, twM, act);
   }
 }
 
-// K-G: g_v = h'(eta_v) (chi(c) + e_v) + 2 w eta_v (1 - eta_v)(1 - 2 eta_v).
 template <typename T, int M, int RB>
 __global__ void __launch_bounds__((RowGeo<M, RB>::THREADS))
-k_xpass_drive(const cx<T>* __restrict__ st, cx<T>* __restrict__ el, Geo g, ModelK m,
-              const cx<T>* twN, const cx<T>* twM) {
+k_xpass_theta(const cx<T>* __restrict__ st, cx<T>* __restrict__ th, Geo g, const cx<T>* twN,
+              const cx<T>* twM) {
+  __shared__ cx<T> lds[RB * RowGeo<M, RB>::LD];
+  body_xpass_theta<T, M, RB>(st, th, g, twN, twM, blockIdx.x, threadIdx.x, lds);
+}
+
+// K-G: g_v = h'(eta_v) (chi(c) + e_v) + 2 w eta_v (1 - eta_v)(1 - 2 eta_v).
+template <typename T, int M, int RB, bool GUARD = false>
+__device__ inline void body_xpass_drive(const cx<T>* st, cx<T>* el, const Geo& g, const ModelK& m,
+                                        const cx<T>* twN, const cx<T>* twM, int tile, int tid, cx<T>* lds) {
   using RG = RowGeo<M, RB>;
-  __shared__ cx<T> lds[RB * RG::LD];
-  const int rl = threadIdx.x / RG::TL;
-  const int bf = threadIdx.x % RG::TL;
-  const int row = blockIdx.x * RB + rl;
-  const bool rvalid = row < g.nz * g.ny;
-  cx<T>* rbuf = lds + rl * RG::LD;
+  const bool act = !GUARD || tid < RG::THREADS;
+  const int rl = tid / RG::TL;
+  const int bf = tid % RG::TL;
+  const int row = tile * RB + rl;
+  const bool rvalid = act && row < g.nz * g.ny;
+  cx<T>* rbuf = lds + (act ? rl : 0) * RG::LD;
   const long long rb = (long long)(rvalid ? row : 0) * g.P;
   const T W = (T)m.W, cm = (T)m.cm, cp = (T)m.cp, w2 = (T)(2.0 * m.w);
   cx<T> chi[RG::R0];
   {
     cx<T> a[RG::R0];
-    row_c2r<T, M, RB>(st + rb, rvalid, a, bf, rbuf, twN, twM);
+    row_c2r<T, M, RB>(st + rb, rvalid, a, bf, rbuf, twN, twM, act);
 #pragma unroll
     for (int t = 0; t < RG::R0; ++t) {
       const T c0 = a[t].re, c1 = a[t].im;
@@ -609,8 +651,8 @@ k_xpass_drive(const cx<T>* __restrict__ st, cx<T>* __restrict__ el, Geo g, Model
   }
   for (int v = 0; v < 3; ++v) {
     cx<T> et[RG::R0], a[RG::R0];
-    row_c2r<T, M, RB>(st + (1 + v) * g.fs + rb, rvalid, et, bf, rbuf, twN, twM);
-    row_c2r<T, M, RB>(el + v * g.fs + rb, rvalid, a, bf, rbuf, twN, twM);
+    row_c2r<T, M, RB>(st + (1 + v) * g.fs + rb, rvalid, et, bf, rbuf, twN, twM, act);
+    row_c2r<T, M, RB>(el + v * g.fs + rb, rvalid, a, bf, rbuf, twN, twM, act);
 #pragma unroll
     for (int t = 0; t < RG::R0; ++t) {
       const T e0 = et[t].re, e1 = et[t].im;
@@ -618,8 +660,16 @@ k_xpass_drive(const cx<T>* __restrict__ st, cx<T>* __restrict__ el, Geo g, Model
       const T g1 = dhfun(e1) * (chi[t].im + a[t].im) + w2 * e1 * ((T)1 - e1) * ((T)1 - (T)2 * e1);
       a[t] = mk<T>(g0, g1);
     }
-    row_r2c<T, M, RB>(a, el + v * g.fs + rb, rvalid, bf, rbuf, twN, twM);
+    row_r2c<T, M, RB>(a, el + v * g.fs + rb, rvalid, bf, rbuf, twN, twM, act);
   }
+}
+
+template <typename T, int M, int RB>
+__global__ void __launch_bounds__((RowGeo<M, RB>::THREADS))
+k_xpass_drive(const cx<T>* __restrict__ st, cx<T>* __restrict__ el, Geo g, ModelK m, const cx<T>* twN,
+              const cx<T>* twM) {
+  __shared__ cx<T> lds[RB * RowGeo<M, RB>::LD];
+  body_xpass_drive<T, M, RB>(st, el, g, m, twN, twM, blockIdx.x, threadIdx.x, lds);
 }
 
 // Standalone row r2c: real rows (length 2M, pitch 2M) -> half-spectrum rows.
@@ -749,6 +799,10 @@ __global__ void __launch_bounds__(256) k_finalize(FinArgs<TE> fa, Geo g) {
   }
 }
 
+// Non-template kernels get internal linkage: this header is included by more
+// than one translation unit.
+namespace {
+
 // Sums n (value, flag) partial pairs in a fixed order into out[0], out[1].
 __global__ void __launch_bounds__(256) k_reduce_pairs(const double* partial, int n, double* out) {
   __shared__ double sh[16];
@@ -783,6 +837,8 @@ __global__ void __launch_bounds__(256) k_vf_partial(const double* u, long long n
     partial[2 * blockIdx.x + 1] = cnt;
   }
 }
+
+}  // namespace
 
 // Element-wise copy with precision conversion over valid k-space entries.
 template <typename TA, typename TB>
