@@ -126,6 +126,96 @@ def cpu_baseline(n=128):
                        "%.1f s; host %s" % (n, wall, platform.processor() or platform.machine()))
 
 
+def ensemble_bench(torch, count, t_final, rtol, atol, ref_members, precisions=("fp64", "mixed")):
+    """64 uneven members: batched (one launch per pass, graph replay) vs one after another."""
+    import pfinputs
+    from paper_2609_36100_amd import Ensemble, Solver
+    mem = pfinputs.ensemble_members(count)
+    kw = dict(adaptive=True, dt0=0.1, rtol=rtol, atol=atol)
+    pts = [m["n"] ** 3 for m in mem]
+    out = dict(members=count, sizes=sorted(set(m["n"] for m in mem)), t_final=t_final, rtol=rtol, atol=atol)
+    vf = {}
+    for prec in precisions:
+        log("ensemble batched %s" % prec)
+        with Ensemble([dict(n=m["n"], precision=prec, **kw) for m in mem]) as E:
+            for i, m in enumerate(mem):
+                E.set_state(i, m["c"], m["eta"])
+            tun = E.autotune(2)
+            for i, m in enumerate(mem):     # the autotuner overwrote scratch only; restart cleanly
+                E.set_state(i, m["c"], m["eta"])
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st = E.advance(t_final)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            vf[prec] = [E.diagnostics(i)["vf"] for i in range(count)]
+        stages = sum(p * s["n_rhs"] for p, s in zip(pts, st))
+        out["batched_" + prec] = dict(wall_s=round(wall, 3), value=round(stages / wall / 1e6, 1),
+                                      steps=sum(s["steps"] for s in st), rejects=sum(s["rejects"] for s in st),
+                                      block_threads={k: v["block_threads"] for k, v in tun.items()})
+    log("ensemble sequential plain fp64")
+    wall = 0.0
+    stages = 0
+    vf_seq = []
+    for i, m in enumerate(mem):
+        with Solver(m["n"], None, method="ark436l", **kw) as s:
+            s.set_state(m["c"], m["eta"])
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st = s.advance(t_final)
+            torch.cuda.synchronize()
+            wall += time.perf_counter() - t0
+            stages += pts[i] * st["n_rhs"]
+            vf_seq.append(s.diagnostics()["vf"])
+    out["sequential_fp64"] = dict(wall_s=round(wall, 3), value=round(stages / wall / 1e6, 1))
+    out["speedup_batched_fp64_vs_sequential"] = round(wall / out["batched_fp64"]["wall_s"], 3)
+    # volume-fraction error against a tighter-tolerance plain FP64 reference
+    log("ensemble reference runs (rtol 1e-8) for %d members" % ref_members)
+    errs = {k: [] for k in list(vf) + ["sequential_fp64"]}
+    for i in range(min(ref_members, count)):
+        m = mem[i]
+        with Solver(m["n"], None, method="ark436l", adaptive=True, dt0=0.05, rtol=1e-8, atol=1e-11) as s:
+            s.set_state(m["c"], m["eta"])
+            s.advance(t_final)
+            ref = s.diagnostics()["vf"]
+        for k in vf:
+            errs[k].append(abs(vf[k][i] - ref))
+        errs["sequential_fp64"].append(abs(vf_seq[i] - ref))
+    out["vf_error_max"] = {k: float("%.3e" % max(v)) for k, v in errs.items() if v}
+    return out
+
+
+def time_to_t_bench(torch, n, t_final, rtol, atol, precisions=("fp64", "mixed")):
+    """Adaptive ARK4 run of the seeded n^3 workload to t_final; vf error against rtol 1e-8."""
+    import pfinputs
+    from paper_2609_36100_amd import Solver
+    spec, c, eta = pfinputs.config("adaptive256", n=n)
+    out = dict(n=n, t_final=t_final, rtol=rtol, atol=atol, nuclei=spec["n_nuclei"])
+    vf = {}
+    for prec in precisions:
+        log("time-to-t %s" % prec)
+        with Solver(n, None, method="ark436l", precision=prec, adaptive=True, dt0=0.1, rtol=rtol, atol=atol) as s:
+            s.set_state(c, eta)
+            s.autotune(2)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st = s.advance(t_final)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            vf[prec] = s.diagnostics()["vf"]
+        out[prec] = dict(wall_s=round(wall, 3), steps=st["steps"], rejects=st["rejects"],
+                         value=round(n ** 3 * st["n_rhs"] / wall / 1e6, 1), vf=vf[prec])
+    log("time-to-t reference (rtol 1e-8)")
+    with Solver(n, None, method="ark436l", adaptive=True, dt0=0.05, rtol=1e-8, atol=1e-11) as s:
+        s.set_state(c, eta)
+        s.advance(t_final)
+        ref = s.diagnostics()["vf"]
+    out["vf_ref"] = ref
+    for prec in precisions:
+        out[prec]["vf_error"] = float("%.3e" % abs(vf[prec] - ref))
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -136,6 +226,9 @@ def main():
     ap.add_argument("--skip-mixed", action="store_true")
     ap.add_argument("--skip-fft", action="store_true")
     ap.add_argument("--skip-cpu", action="store_true")
+    ap.add_argument("--mode", choices=["throughput", "ensemble", "time_to_t"], default="throughput")
+    ap.add_argument("--t-final", type=float, default=None)
+    ap.add_argument("--members", type=int, default=64)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 4 GiB (counter calibration)")
     args = ap.parse_args()
@@ -158,6 +251,24 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read_per_launch": src.numel() * 8,
                           "copy_bytes_written_per_launch": src.numel() * 8, "launches": 3}))
+        return
+    if args.mode == "ensemble":
+        r = ensemble_bench(torch, args.members, args.t_final or 100.0, 1e-6, 1e-9, ref_members=8)
+        print(json.dumps({"metric": METRIC, "mode": "ensemble", "unit": "Mpts·stages/s",
+                          "value": r["batched_fp64"]["value"], "n_gpus": 1, "dtype": "f64",
+                          "data": "synthetic", "higher_is_better": True,
+                          "config": {"workload": "%d seeded members of sizes %s, adaptive ARK4(3)6L to t=%g"
+                                                 % (args.members, r["sizes"], r["t_final"])},
+                          "ensemble": r}), flush=True)
+        return
+    if args.mode == "time_to_t":
+        n = args.n if args.n != 512 else 256
+        r = time_to_t_bench(torch, n, args.t_final or 500.0, 1e-6, 1e-9)
+        print(json.dumps({"metric": METRIC, "mode": "time_to_t", "unit": "s", "value": r["fp64"]["wall_s"],
+                          "higher_is_better": False, "n_gpus": 1, "dtype": "f64", "data": "synthetic",
+                          "config": {"workload": "%d^3, %d seeded nuclei, adaptive ARK4(3)6L rtol 1e-6 to t=%g"
+                                                 % (n, r["nuclei"], r["t_final"])},
+                          "time_to_t": r}), flush=True)
         return
     n = args.n
     log("generating %d^3 seeded initial condition" % n)
