@@ -242,6 +242,47 @@ pf_status pf_ensemble_tuning_get(pf_ens* ens, int32_t kind, int32_t* block_threa
                                  double* ms256);
 pf_status pf_ensemble_tuning_set(pf_ens* ens, int32_t kind, int32_t block_threads);
 
+/* ---- Fourier neural operator surrogate (learned form) --------------------
+ * Maps the real-space state (cin = 4 fields c, eta_1..3 on an n^3 grid,
+ * planar [field][z][y][x]) to the state a fixed time later: the network
+ * predicts the increment divided by a per-channel scale.  Layers:
+ * v0 = x W_lift + b_lift; v_{l+1} = GELU(K_l v_l + v_l W_l + b_l) (the last
+ * layer without GELU), K_l = inverse truncated DFT . per-mode complex width x
+ * width matrix . forward truncated DFT (kx < modes; ky, kz among the `modes`
+ * lowest non-negative and negative frequencies); out = GELU(v_L P1 + c1) P2 + c2.
+ * BF16 weights and activations, FP32 accumulation (MFMA), FP32 master
+ * weights with Adam.  Parameters are one flat float32 vector in the order
+ * W_lift (cin x width), b_lift, per layer {R_re, R_im ([2m][2m][m][width][width]),
+ * W (width x width), b}, P1 (width x hidden), c1, P2 (hidden x cout), c2.
+ * Constraints: n % 8 == 0, 8 <= n <= 256, width % 4 == 0 (<= 128), modes even,
+ * 2 modes <= n, hidden % 8 == 0 (<= 128), cin, cout <= 8. */
+typedef struct {
+  int32_t n, width, modes, layers, hidden, cin, cout;
+} pf_fno_config;
+typedef struct pf_fno pf_fno;
+pf_status pf_fno_create(const pf_fno_config* cfg, void* hip_stream, pf_fno** out);
+void pf_fno_destroy(pf_fno* f);
+int64_t pf_fno_num_params(const pf_fno* f);
+/* host float32 arrays of pf_fno_num_params values; set also resets Adam */
+pf_status pf_fno_set_params(pf_fno* f, const float* host_params);
+pf_status pf_fno_get_params(pf_fno* f, float* host_params);
+/* per-channel output scale (cout host floats); the target is (y - x) / scale */
+pf_status pf_fno_set_scale(pf_fno* f, const float* host_scale);
+/* network output for x (device float32 [cin][n^3]) into out (device float32
+ * [n^3][cout], point-major) */
+pf_status pf_fno_forward(pf_fno* f, const float* x, float* out);
+/* forward + mean-squared loss against the target (y - x) / scale (x, y device
+ * float32 [cin][n^3]) + backward; gradients are ADDED to the gradient buffer */
+pf_status pf_fno_grad(pf_fno* f, const float* x, const float* y, double* loss);
+pf_status pf_fno_get_grad(pf_fno* f, float* host_grad);
+pf_status pf_fno_zero_grad(pf_fno* f);
+/* Adam step with the accumulated gradient times grad_scale; zeroes it */
+pf_status pf_fno_adam_step(pf_fno* f, float lr, float beta1, float beta2, float eps, float grad_scale);
+/* surrogate advance: next = state + scale * net(state), then the mean of c is
+ * restored (the composition is conserved); state / next device float64
+ * [cin][n^3] (cin == cout) */
+pf_status pf_fno_apply(pf_fno* f, const double* state, double* next);
+
 /* Human-readable status name; never NULL. */
 const char* pf_status_string(pf_status s);
 

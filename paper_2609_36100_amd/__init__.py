@@ -14,7 +14,7 @@ import numpy as np
 from . import _lib
 from ._lib import PFError, Stats, make_params  # noqa: F401
 
-__all__ = ["Solver", "Ensemble", "PFError", "make_params", "size_supported"]
+__all__ = ["Solver", "Ensemble", "FNO", "PFError", "make_params", "size_supported"]
 
 
 def _torch():
@@ -308,3 +308,82 @@ class Ensemble:
     def set_tuning(self, kind, block_threads):
         _lib.check(_lib.lib().pf_ensemble_tuning_set(self._h, int(kind), int(block_threads)),
                    "pf_ensemble_tuning_set")
+
+
+class FNO:
+    """Fourier neural operator surrogate on the GPU (BF16 MFMA, FP32 master weights).
+
+    Parameters are a flat float32 vector (see ``pf_fno_set_params``); inputs
+    and targets are device float32 tensors of shape (cin, n, n, n).
+    """
+
+    def __init__(self, n, width=32, modes=12, layers=4, hidden=None, cin=4, cout=4, stream=None):
+        torch = _torch()
+        if not torch.cuda.is_available():
+            raise RuntimeError("libpf needs a GPU (gfx950); none is visible")
+        self.cfg = _lib.FnoConfig(n, width, modes, layers, hidden if hidden else 4 * width, cin, cout)
+        self._stream = stream if stream is not None else torch.cuda.current_stream()
+        h = ctypes.c_void_p()
+        _lib.check(_lib.lib().pf_fno_create(ctypes.byref(self.cfg), ctypes.c_void_p(self._stream.cuda_stream),
+                                            ctypes.byref(h)), "pf_fno_create")
+        self._h = h
+        self.n, self.cin, self.cout = n, cin, cout
+        self.num_params = int(_lib.lib().pf_fno_num_params(h))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.lib().pf_fno_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def set_params(self, theta):
+        th = np.ascontiguousarray(theta, dtype=np.float32)
+        assert th.size == self.num_params
+        _lib.check(_lib.lib().pf_fno_set_params(self._h, th.ctypes.data_as(ctypes.c_void_p)), "pf_fno_set_params")
+
+    def get_params(self):
+        th = np.empty(self.num_params, np.float32)
+        _lib.check(_lib.lib().pf_fno_get_params(self._h, th.ctypes.data_as(ctypes.c_void_p)), "pf_fno_get_params")
+        return th
+
+    def set_scale(self, scale):
+        sc = np.ascontiguousarray(scale, dtype=np.float32)
+        _lib.check(_lib.lib().pf_fno_set_scale(self._h, sc.ctypes.data_as(ctypes.c_void_p)), "pf_fno_set_scale")
+
+    def forward(self, x):
+        torch = _torch()
+        out = torch.empty((self.n ** 3, self.cout), dtype=torch.float32, device="cuda")
+        _lib.check(_lib.lib().pf_fno_forward(self._h, _ptr(x.contiguous()), _ptr(out)), "pf_fno_forward")
+        return out
+
+    def grad(self, x, y):
+        loss = ctypes.c_double()
+        _lib.check(_lib.lib().pf_fno_grad(self._h, _ptr(x.contiguous()), _ptr(y.contiguous()), ctypes.byref(loss)),
+                   "pf_fno_grad")
+        return loss.value
+
+    def get_grad(self):
+        g = np.empty(self.num_params, np.float32)
+        _lib.check(_lib.lib().pf_fno_get_grad(self._h, g.ctypes.data_as(ctypes.c_void_p)), "pf_fno_get_grad")
+        return g
+
+    def zero_grad(self):
+        _lib.check(_lib.lib().pf_fno_zero_grad(self._h), "pf_fno_zero_grad")
+
+    def adam_step(self, lr, beta1=0.9, beta2=0.999, eps=1e-8, grad_scale=1.0):
+        _lib.check(_lib.lib().pf_fno_adam_step(self._h, lr, beta1, beta2, eps, grad_scale), "pf_fno_adam_step")
+
+    def apply(self, state, out):
+        """out = state + scale * net(state), mean of c restored (device float64 (cin, n, n, n))."""
+        _lib.check(_lib.lib().pf_fno_apply(self._h, _ptr(state), _ptr(out)), "pf_fno_apply")

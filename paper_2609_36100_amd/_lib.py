@@ -41,6 +41,12 @@ class Params(ctypes.Structure):
     ]
 
 
+class FnoConfig(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("width", ctypes.c_int32), ("modes", ctypes.c_int32),
+                ("layers", ctypes.c_int32), ("hidden", ctypes.c_int32), ("cin", ctypes.c_int32),
+                ("cout", ctypes.c_int32)]
+
+
 class Stats(ctypes.Structure):
     _fields_ = [
         ("steps", ctypes.c_int64), ("attempts", ctypes.c_int64),
@@ -112,6 +118,20 @@ _SIGS = {
     "pf_ensemble_tuning_get": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
                                               ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
     "pf_ensemble_tuning_set": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32]),
+    "pf_fno_create": (ctypes.c_int, [ctypes.POINTER(FnoConfig), ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
+    "pf_fno_destroy": (None, [ctypes.c_void_p]),
+    "pf_fno_num_params": (ctypes.c_int64, [ctypes.c_void_p]),
+    "pf_fno_set_params": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "pf_fno_get_params": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "pf_fno_set_scale": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "pf_fno_forward": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "pf_fno_grad": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                   ctypes.POINTER(ctypes.c_double)]),
+    "pf_fno_get_grad": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "pf_fno_zero_grad": (ctypes.c_int, [ctypes.c_void_p]),
+    "pf_fno_adam_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                        ctypes.c_float, ctypes.c_float]),
+    "pf_fno_apply": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "pf_profile_enable": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "pf_profile_classes": (ctypes.c_int32, []),
     "pf_profile_name": (ctypes.c_char_p, [ctypes.c_int32]),

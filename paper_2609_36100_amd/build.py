@@ -7,7 +7,7 @@ import sys
 import time
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SRCS = [os.path.join(HERE, "csrc", f) for f in ("pf_runtime.hip", "pf_ensemble.hip")]
+SRCS = [os.path.join(HERE, "csrc", f) for f in ("pf_runtime.hip", "pf_ensemble.hip", "pf_fno.hip")]
 OUT = os.path.join(HERE, "libpf.so")
 OBJDIR = os.path.join(HERE, "_build")
 

@@ -1,0 +1,800 @@
+// Fourier neural operator surrogate: BF16 MFMA training and inference on gfx950.
+//
+// The learned form beside the method: a classic FNO maps the state
+// (c, eta_1..3) on an n^3 grid to the increment of the state a fixed time
+// later.  Architecture (width w, modes m, L layers, hidden h):
+//   v0 = x W_lift + b_lift;  v_{l+1} = act(K_l v_l + v_l W_l + b_l);
+//   out = GELU(v_L P1 + c1) P2 + c2,
+//   K_l v = inverse truncated DFT( R_l . forward truncated DFT(v) ),
+// retained modes kx < m and ky, kz in the m lowest positive and negative
+// frequencies.  Activations are channel-last [point][channel] BF16.
+//
+// Dense contractions run on MFMA (v_mfma_f32_32x32x8bf16_1k, FP32 accumulate):
+//  * channel mixing (lift, W_l, P1, P2 and their data gradients) as
+//    [points x K] x [K x N] GEMMs;
+//  * every truncated-DFT stage as a small constant matrix G times batched
+//    activation blocks, Out_b = G X_b, with layouts chosen so each stage is a
+//    plain strided GEMM (and its backward the same kernel with G^T).
+// The per-mode complex w x w mixing and the weight-gradient reductions over
+// points run on FP32 vector ALUs.  Adam updates FP32 master weights and
+// refreshes the BF16 working copies.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/pf.h"
+
+namespace {
+
+typedef unsigned short u16;
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+__host__ __device__ inline u16 f2bf(float f) {
+  unsigned int u;
+  std::memcpy(&u, &f, 4);
+  u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest even
+  return (u16)(u >> 16);
+}
+__host__ __device__ inline float bf2f(u16 h) {
+  unsigned int u = ((unsigned int)h) << 16;
+  float f;
+  std::memcpy(&f, &u, 4);
+  return f;
+}
+
+__device__ inline float gelu_f(float x) { return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f)); }
+__device__ inline float gelu_g(float x) {
+  return 0.5f * (1.0f + erff(x * 0.70710678118654752f)) + x * 0.39894228040143268f * expf(-0.5f * x * x);
+}
+
+__device__ inline bf16x4 ld4(const u16* p) { return *reinterpret_cast<const bf16x4*>(p); }
+
+// ---- channel-mixing GEMM: Out[p][n] = epi(sum_k In[p][k] Bt[n][k]) ----------
+// K % 4 == 0 (zero beyond K), P % 128 == 0, N <= 32 * NT.  Epilogue: + bias[n] + resid[p][n],
+// stores any of: f32 result, bf16 pre-activation, bf16 GELU(pre).
+template <int NT>
+__global__ void __launch_bounds__(256)
+k_cm_gemm(const u16* __restrict__ In, int ldin, int K, const u16* __restrict__ Bt, int N,
+          const float* __restrict__ bias, const float* __restrict__ resid, int ldres, float* __restrict__ outf,
+          u16* __restrict__ outpre, u16* __restrict__ outact, int ldout, int accumulate) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const long long p0 = ((long long)blockIdx.x * 4 + wave) * 32;
+  const int lr = lane & 31, lg = lane >> 5;
+  f32x16 acc[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+#pragma unroll
+    for (int i = 0; i < 16; ++i) acc[t][i] = 0.0f;
+  for (int kk = 0; kk < K; kk += 8) {
+    const bool kin = kk + lg * 4 < K;  // K % 4 == 0: a 4-wide group is all in or all out
+    bf16x4 a = {0, 0, 0, 0};
+    if (kin) a = ld4(In + (p0 + lr) * ldin + kk + lg * 4);
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const int n = t * 32 + lr;
+      bf16x4 b = {0, 0, 0, 0};
+      if (n < N && kin) b = ld4(Bt + (long long)n * K + kk + lg * 4);
+      acc[t] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc[t], 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const int col = t * 32 + lr;
+    if (col >= N) continue;
+    const float bb = bias ? bias[col] : 0.0f;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const long long row = p0 + 8 * (i >> 2) + 4 * lg + (i & 3);
+      float v = acc[t][i] + bb;
+      if (resid) v += resid[row * ldres + col];
+      const long long o = row * ldout + col;
+      if (outf) outf[o] = accumulate ? outf[o] + v : v;
+      if (outpre) outpre[o] = f2bf(v);
+      if (outact) outact[o] = f2bf(gelu_f(v));
+    }
+  }
+}
+
+// ---- small-matrix GEMM: Out_b[r][n] = sum_k G[r][k] X_b[k][n] ---------------
+// G row-major R x K (K % 4 == 0, zero beyond K), X_b rows of stride ldx,
+// batch stride xbs.
+// Each wave owns 32 columns and 4 row tiles (128 rows) per pass.
+__global__ void __launch_bounds__(256)
+k_lm_gemm(const u16* __restrict__ G, int R, int K, const u16* __restrict__ X, long long xbs, int ldx, int Nc,
+          float* __restrict__ outf, u16* __restrict__ outb, long long obs, int ldo, int accumulate) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int lr = lane & 31, lg = lane >> 5;
+  const long long b = blockIdx.y;
+  const int n = (blockIdx.x * 4 + wave) * 32 + lr;
+  const bool valid = n < Nc;
+  const u16* Xb = X + b * xbs;
+  for (int r0 = 0; r0 < R; r0 += 128) {
+    f32x16 acc[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int i = 0; i < 16; ++i) acc[t][i] = 0.0f;
+    for (int kk = 0; kk < K; kk += 8) {
+      const int kb = kk + lg * 4;
+      const bool kin = kb < K;  // K % 4 == 0
+      bf16x4 bv = {0, 0, 0, 0};
+      if (valid && kin) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) bv[j] = (short)Xb[(long long)(kb + j) * ldx + n];
+      }
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int r = r0 + t * 32 + lr;
+        if (r0 + t * 32 < R) {
+          bf16x4 av = {0, 0, 0, 0};
+          if (r < R && kin) av = ld4(G + (long long)r * K + kb);
+          acc[t] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(av, bv, acc[t], 0, 0, 0);
+        }
+      }
+    }
+    if (valid) {
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+          const int row = r0 + t * 32 + 8 * (i >> 2) + 4 * lg + (i & 3);
+          if (row >= R) continue;
+          const long long o = b * obs + (long long)row * ldo + n;
+          const float v = acc[t][i];
+          if (outf) outf[o] = accumulate ? outf[o] + v : v;
+          if (outb) outb[o] = f2bf(accumulate ? bf2f(outb[o]) + v : v);
+        }
+    }
+  }
+}
+
+// ---- per-mode complex mixing (FP32) -------------------------------------------
+// S, T: [2][modes][w] (real block, imaginary block); R: [modes][w][w] (in, out).
+__global__ void __launch_bounds__(256)
+k_mix_fwd(const float* __restrict__ S, const u16* __restrict__ Rr, const u16* __restrict__ Ri, float* __restrict__ T,
+          int modes, int w, u16* __restrict__ Tb) {
+  const long long id = blockIdx.x * 256LL + threadIdx.x;
+  if (id >= (long long)modes * w) return;
+  const long long md = id / w;
+  const int o = (int)(id % w);
+  const long long mo = (long long)modes * w;
+  float tr = 0.f, ti = 0.f;
+  for (int i = 0; i < w; ++i) {
+    const float sr = S[md * w + i], si = S[mo + md * w + i];
+    const float rr = bf2f(Rr[(md * w + i) * w + o]), ri = bf2f(Ri[(md * w + i) * w + o]);
+    tr += rr * sr - ri * si;
+    ti += rr * si + ri * sr;
+  }
+  T[md * w + o] = tr;
+  T[mo + md * w + o] = ti;
+  Tb[md * w + o] = f2bf(tr);
+  Tb[mo + md * w + o] = f2bf(ti);
+}
+
+__global__ void __launch_bounds__(256)
+k_mix_bwd_data(const float* __restrict__ dT, const u16* __restrict__ Rr, const u16* __restrict__ Ri,
+               u16* __restrict__ dSb, int modes, int w) {
+  const long long id = blockIdx.x * 256LL + threadIdx.x;
+  if (id >= (long long)modes * w) return;
+  const long long md = id / w;
+  const int i = (int)(id % w);
+  const long long mo = (long long)modes * w;
+  float sr = 0.f, si = 0.f;
+  for (int o = 0; o < w; ++o) {
+    const float tr = dT[md * w + o], ti = dT[mo + md * w + o];
+    const float rr = bf2f(Rr[(md * w + i) * w + o]), ri = bf2f(Ri[(md * w + i) * w + o]);
+    sr += rr * tr + ri * ti;
+    si += rr * ti - ri * tr;
+  }
+  dSb[md * w + i] = f2bf(sr);
+  dSb[mo + md * w + i] = f2bf(si);
+}
+
+__global__ void __launch_bounds__(256)
+k_mix_bwd_w(const float* __restrict__ S, const float* __restrict__ dT, float* __restrict__ gRr,
+            float* __restrict__ gRi, int modes, int w) {
+  const long long id = blockIdx.x * 256LL + threadIdx.x;
+  if (id >= (long long)modes * w * w) return;
+  const long long md = id / (w * w);
+  const int i = (int)((id / w) % w), o = (int)(id % w);
+  const long long mo = (long long)modes * w;
+  const float sr = S[md * w + i], si = S[mo + md * w + i];
+  const float tr = dT[md * w + o], ti = dT[mo + md * w + o];
+  gRr[id] += sr * tr + si * ti;
+  gRi[id] += sr * ti - si * tr;
+}
+
+// ---- weight gradients: G[k][n] += sum_p A[p][k] D[p][n], bias row k = K ------
+// Partial sums per block over a chunk of points; k_sum_partials adds them.
+__global__ void __launch_bounds__(256)
+k_wgrad_partial(const u16* __restrict__ A, int lda, int K, const float* __restrict__ D, int ldd, int N,
+                long long P, int chunk, float* __restrict__ part) {
+  const int KN = (K + 1) * N;
+  const long long p_begin = (long long)blockIdx.x * chunk;
+  const long long p_end = p_begin + chunk < P ? p_begin + chunk : P;
+  for (int e = threadIdx.x; e < KN; e += 256) {
+    const int k = e / N, n = e % N;
+    float s = 0.f;
+    for (long long p = p_begin; p < p_end; ++p) {
+      const float a = k < K ? bf2f(A[p * lda + k]) : 1.0f;
+      s += a * D[p * ldd + n];
+    }
+    part[(long long)blockIdx.x * KN + e] = s;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_sum_partials(const float* __restrict__ part, int nb, int KN,
+                                                      float* __restrict__ gW, float* __restrict__ gb, int K, int N) {
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= KN) return;
+  float s = 0.f;
+  for (int b = 0; b < nb; ++b) s += part[(long long)b * KN + e];
+  const int k = e / N, n = e % N;
+  if (k < K)
+    gW[k * N + n] += s;
+  else
+    gb[n] += s;
+}
+
+// ---- elementwise ------------------------------------------------------------------
+// dpre = dpost * GELU'(pre) (or dpost when last), f32 and bf16 copies.
+__global__ void __launch_bounds__(256) k_gelu_bwd(const float* __restrict__ dpost, const u16* __restrict__ pre,
+                                                  float* __restrict__ dpre, u16* __restrict__ dpreb, long long n,
+                                                  int linear) {
+  const long long i = blockIdx.x * 256LL + threadIdx.x;
+  if (i >= n) return;
+  const float g = linear ? dpost[i] : dpost[i] * gelu_g(bf2f(pre[i]));
+  dpre[i] = g;
+  dpreb[i] = f2bf(g);
+}
+
+// planar f32 [cin][P] (or f64) -> bf16 [P][ld] zero padded
+template <typename TI>
+__global__ void __launch_bounds__(256) k_pack_input(const TI* __restrict__ x, long long P, int cin, int ld,
+                                                    u16* __restrict__ out) {
+  const long long p = blockIdx.x * 256LL + threadIdx.x;
+  if (p >= P) return;
+  for (int c = 0; c < ld; ++c) out[p * ld + c] = c < cin ? f2bf((float)x[c * P + p]) : (u16)0;
+}
+
+// loss: out f32 [P][co] vs target (y - x) / scale (planar f32); writes dout
+// (bf16 [P][ldd] padded, f32 [P][co]) and per-block squared-error partials
+__global__ void __launch_bounds__(256) k_loss(const float* __restrict__ out, const float* __restrict__ x,
+                                              const float* __restrict__ y, const float* __restrict__ scale,
+                                              long long P, int co, int ldd, float* __restrict__ doutf,
+                                              u16* __restrict__ doutb, double* __restrict__ part) {
+  __shared__ double sh[4];
+  const long long p = blockIdx.x * 256LL + threadIdx.x;
+  double s = 0.0;
+  if (p < P) {
+    const float inv = 2.0f / (float)((double)P * co);
+    for (int c = 0; c < ldd; ++c) {
+      float g = 0.f;
+      if (c < co) {
+        const float tgt = (y[c * P + p] - x[c * P + p]) / scale[c];
+        const float d = out[p * co + c] - tgt;
+        s += (double)d * d;
+        g = d * inv;
+        doutf[p * co + c] = g;
+      }
+      doutb[p * ldd + c] = f2bf(g);
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0] + sh[1] + sh[2] + sh[3];
+}
+
+__global__ void __launch_bounds__(256) k_sum_d(const double* __restrict__ part, int n, double* __restrict__ out) {
+  __shared__ double sh[4];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) s += part[i];
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) out[0] = sh[0] + sh[1] + sh[2] + sh[3];
+}
+
+// Adam on FP32 master weights; the gradient buffer is consumed (zeroed).
+__global__ void __launch_bounds__(256) k_adam(float* __restrict__ th, float* __restrict__ m, float* __restrict__ v,
+                                              float* __restrict__ g, long long n, float lr, float b1, float b2,
+                                              float eps, float gscale, float c1, float c2) {
+  const long long i = blockIdx.x * 256LL + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i] * gscale;
+  const float mi = b1 * m[i] + (1.f - b1) * gi;
+  const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  th[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+  g[i] = 0.f;
+}
+
+// bf16 working copies: dst[r][c] = src[r*sr + c*sc] (transposes and padding)
+__global__ void __launch_bounds__(256) k_to_bf16(const float* __restrict__ src, int rows, int cols, int ld_dst,
+                                                 long long sr, long long sc, u16* __restrict__ dst) {
+  const long long i = blockIdx.x * 256LL + threadIdx.x;
+  if (i >= (long long)rows * ld_dst) return;
+  const int r = (int)(i / ld_dst), c = (int)(i % ld_dst);
+  dst[i] = c < cols ? f2bf(src[r * sr + c * sc]) : (u16)0;
+}
+
+// new_state[f][p] = state[f][p] + scale[f] * out[p][f]  (f64 planar state)
+__global__ void __launch_bounds__(256) k_apply(const double* __restrict__ st, const float* __restrict__ out,
+                                               const float* __restrict__ scale, long long P, int co,
+                                               double* __restrict__ res, double* __restrict__ part) {
+  __shared__ double sh[4];
+  const long long p = blockIdx.x * 256LL + threadIdx.x;
+  double dc = 0.0;
+  if (p < P) {
+    for (int f = 0; f < co; ++f) {
+      const double d = (double)scale[f] * (double)out[p * co + f];
+      res[f * P + p] = st[f * P + p] + d;
+      if (f == 0) dc = d;
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) dc += __shfl_xor(dc, o, 64);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = dc;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = sh[0] + sh[1] + sh[2] + sh[3];
+}
+
+// mass correction: c -= mean increment of c (the composition is conserved)
+__global__ void __launch_bounds__(256) k_shift(double* __restrict__ c, long long P, const double* __restrict__ sum) {
+  const long long p = blockIdx.x * 256LL + threadIdx.x;
+  if (p < P) c[p] -= sum[0] / (double)P;
+}
+
+}  // namespace
+
+// ---- host side ----------------------------------------------------------------
+struct pf_fno {
+  pf_fno_config cfg;
+  hipStream_t stream = nullptr;
+  long long P = 0;
+  int mode_count = 0;   // (2m)^2 m
+  int cinp = 8, coutp = 8;  // padded channel counts (K % 8)
+  int64_t nparams = 0;
+  // parameter offsets in the flat FP32 vector
+  long long o_Wl, o_bl, o_P1, o_c1, o_P2, o_c2;
+  std::vector<long long> o_Rr, o_Ri, o_W, o_b;
+  float *th = nullptr, *gr = nullptr, *am = nullptr, *av = nullptr;
+  long long adam_t = 0;
+  // bf16 working weights
+  u16 *bWliftT = nullptr, *bP1T = nullptr, *bP1 = nullptr, *bP2T = nullptr, *bP2 = nullptr;
+  std::vector<u16*> bWT, bW, bRr, bRi;
+  // DFT matrices (forward and inverse stages, and their transposes)
+  u16 *Gxf, *Gyf, *Gzf, *Gxi, *Gyi, *Gzi, *GxfT, *GyfT, *GzfT, *GxiT, *GyiT, *GziT;
+  float* scale = nullptr;  // output scale per channel
+  // activations
+  u16* xin = nullptr;
+  std::vector<u16*> v, pre;
+  std::vector<float*> S;
+  u16 *hpre = nullptr, *hact = nullptr;
+  u16 *A1 = nullptr, *A2 = nullptr, *A3 = nullptr, *Tb = nullptr, *B3 = nullptr, *B2 = nullptr;
+  float *T = nullptr, *B1 = nullptr, *outf = nullptr;
+  // backward buffers
+  float *dvf = nullptr, *dvf2 = nullptr, *dpref = nullptr, *dT = nullptr, *dhf = nullptr;
+  u16 *dvb = nullptr, *dpreb = nullptr, *douthb = nullptr, *dhb = nullptr, *dSb = nullptr;
+  float* part = nullptr;
+  long long part_elems = 0;
+  double* dpart = nullptr;
+  double* dsum = nullptr;
+  double* hsum = nullptr;  // pinned
+  std::vector<void*> allocs;
+};
+
+#define FH(call)                                     \
+  do {                                               \
+    if ((call) != hipSuccess) return PF_ERR_HIP;     \
+  } while (0)
+
+static pf_status falloc(pf_fno* F, void** p, size_t bytes) {
+  if (hipMalloc(p, bytes) != hipSuccess) {
+    *p = nullptr;
+    return PF_ERR_OOM;
+  }
+  F->allocs.push_back(*p);
+  return PF_OK;
+}
+
+static inline unsigned gdiv(long long n, int b) { return (unsigned)((n + b - 1) / b); }
+
+// Real DFT matrices for the six stages (see the header comment of this file).
+static void build_dft(int n, int m, std::vector<std::vector<float>>& out) {
+  const double pi = 3.14159265358979323846;
+  std::vector<int> kx(m), kyz(2 * m);
+  for (int i = 0; i < m; ++i) kx[i] = i;
+  for (int i = 0; i < m; ++i) kyz[i] = i, kyz[m + i] = n - m + i;
+  const int m2 = 2 * m;
+  // x forward: rows (ri, kx) 2m, cols x n
+  std::vector<float> xf(2 * m * n), xi(n * 2 * m), yf(2 * m2 * 2 * n), yi(2 * n * 2 * m2);
+  for (int k = 0; k < m; ++k)
+    for (int x = 0; x < n; ++x) {
+      const double a = 2 * pi * kx[k] * x / n;
+      xf[(0 * m + k) * n + x] = (float)cos(a);
+      xf[(1 * m + k) * n + x] = (float)(-sin(a));
+      const double w = (kx[k] == 0 ? 1.0 : 2.0) / ((double)n * n * n);
+      xi[x * 2 * m + 0 * m + k] = (float)(w * cos(a));
+      xi[x * 2 * m + 1 * m + k] = (float)(-w * sin(a));
+    }
+  // y / z forward: rows (ro, k) 2*m2, cols (y, ri) 2n ; inverse: rows (y, ro) 2n, cols (ri, k) 2*m2
+  for (int k = 0; k < m2; ++k)
+    for (int y = 0; y < n; ++y) {
+      const double a = 2 * pi * kyz[k] * y / n;
+      const float C = (float)cos(a), S = (float)sin(a);
+      const int K2 = 2 * n;
+      yf[(0 * m2 + k) * K2 + y * 2 + 0] = C;
+      yf[(0 * m2 + k) * K2 + y * 2 + 1] = S;
+      yf[(1 * m2 + k) * K2 + y * 2 + 0] = -S;
+      yf[(1 * m2 + k) * K2 + y * 2 + 1] = C;
+      const int Kq = 2 * m2;
+      yi[(y * 2 + 0) * Kq + 0 * m2 + k] = C;
+      yi[(y * 2 + 0) * Kq + 1 * m2 + k] = -S;
+      yi[(y * 2 + 1) * Kq + 0 * m2 + k] = S;
+      yi[(y * 2 + 1) * Kq + 1 * m2 + k] = C;
+    }
+  out = {xf, yf, yf, xi, yi, yi};
+}
+
+static std::vector<float> transpose(const std::vector<float>& a, int R, int K) {
+  std::vector<float> t((size_t)R * K);
+  for (int r = 0; r < R; ++r)
+    for (int k = 0; k < K; ++k) t[(size_t)k * R + r] = a[(size_t)r * K + k];
+  return t;
+}
+
+static pf_status upload_bf16(pf_fno* F, const std::vector<float>& h, u16** d) {
+  std::vector<u16> b(h.size());
+  for (size_t i = 0; i < h.size(); ++i) b[i] = f2bf(h[i]);
+  pf_status s = falloc(F, (void**)d, sizeof(u16) * b.size());
+  if (s != PF_OK) return s;
+  if (hipMemcpy(*d, b.data(), sizeof(u16) * b.size(), hipMemcpyHostToDevice) != hipSuccess) return PF_ERR_HIP;
+  return PF_OK;
+}
+
+static void lm(pf_fno* F, const u16* G, int R, int K, const u16* X, long long xbs, int ldx, int Nc, int batches,
+               float* outf, u16* outb, long long obs, int ldo, int accumulate) {
+  dim3 grid(gdiv(Nc, 128), batches);
+  k_lm_gemm<<<grid, 256, 0, F->stream>>>(G, R, K, X, xbs, ldx, Nc, outf, outb, obs, ldo, accumulate);
+}
+
+static void cm(pf_fno* F, const u16* In, int ldin, int K, const u16* Bt, int N, const float* bias, const float* resid,
+               int ldres, float* outf, u16* outpre, u16* outact, int ldout, int accumulate) {
+  const unsigned grid = (unsigned)(F->P / 128);
+  if (N <= 32)
+    k_cm_gemm<1><<<grid, 256, 0, F->stream>>>(In, ldin, K, Bt, N, bias, resid, ldres, outf, outpre, outact, ldout,
+                                               accumulate);
+  else
+    k_cm_gemm<4><<<grid, 256, 0, F->stream>>>(In, ldin, K, Bt, N, bias, resid, ldres, outf, outpre, outact, ldout,
+                                               accumulate);
+}
+
+static void wgrad(pf_fno* F, const u16* A, int lda, int K, const float* D, int ldd, int N, float* gW, float* gb) {
+  const int chunk = 2048;
+  const int nb = (int)gdiv(F->P, chunk);
+  const int KN = (K + 1) * N;
+  k_wgrad_partial<<<nb, 256, 0, F->stream>>>(A, lda, K, D, ldd, N, F->P, chunk, F->part);
+  k_sum_partials<<<gdiv(KN, 256), 256, 0, F->stream>>>(F->part, nb, KN, gW, gb, K, N);
+}
+
+// refresh the bf16 working weights from the FP32 master vector
+static void refresh(pf_fno* F) {
+  const pf_fno_config& c = F->cfg;
+  const int w = c.width, h = c.hidden;
+  hipStream_t s = F->stream;
+  auto cvt = [&](long long off, int rows, int cols, int ld, long long sr, long long sc, u16* dst) {
+    k_to_bf16<<<gdiv((long long)rows * ld, 256), 256, 0, s>>>(F->th + off, rows, cols, ld, sr, sc, dst);
+  };
+  // W_lift^T [w][cinp]: dst[o][c] = W_lift[c][o]
+  cvt(F->o_Wl, w, c.cin, F->cinp, 1, w, F->bWliftT);
+  for (int l = 0; l < c.layers; ++l) {
+    cvt(F->o_W[l], w, w, w, 1, w, F->bWT[l]);   // W^T[o][i] = W[i][o]
+    cvt(F->o_W[l], w, w, w, w, 1, F->bW[l]);    // W[i][o]
+    const long long nr = (long long)F->mode_count * w * w;
+    k_to_bf16<<<gdiv(nr, 256), 256, 0, s>>>(F->th + F->o_Rr[l], 1, (int)nr, (int)nr, 0, 1, F->bRr[l]);
+    k_to_bf16<<<gdiv(nr, 256), 256, 0, s>>>(F->th + F->o_Ri[l], 1, (int)nr, (int)nr, 0, 1, F->bRi[l]);
+  }
+  cvt(F->o_P1, h, w, w, 1, h, F->bP1T);        // P1^T [h][w]
+  cvt(F->o_P1, w, h, h, h, 1, F->bP1);         // P1 [w][h]
+  cvt(F->o_P2, c.cout, h, h, 1, c.cout, F->bP2T);  // P2^T [cout][h]
+  cvt(F->o_P2, h, c.cout, F->coutp, c.cout, 1, F->bP2);  // P2 [h][coutp]
+}
+
+// forward pass for the packed input F->xin; leaves the result in F->outf
+static void forward(pf_fno* F) {
+  const pf_fno_config& c = F->cfg;
+  const int n = c.n, w = c.width, m = c.modes, m2 = 2 * m, h = c.hidden;
+  const long long P = F->P;
+  const float* th = F->th;
+  cm(F, F->xin, F->cinp, F->cinp, F->bWliftT, w, th + F->o_bl, nullptr, 0, nullptr, F->v[0], nullptr, w, 0);
+  for (int l = 0; l < c.layers; ++l) {
+    const u16* v = F->v[l];
+    // forward truncated DFT: x (batch z,y), y (batch z), z
+    lm(F, F->Gxf, 2 * m, n, v, (long long)n * w, w, w, n * n, nullptr, F->A1, (long long)2 * m * w, w, 0);
+    lm(F, F->Gyf, 2 * m2, 2 * n, F->A1, (long long)n * 2 * m * w, m * w, m * w, n, nullptr, F->A2,
+       (long long)2 * m2 * m * w, m * w, 0);
+    const int Nz = m2 * m * w;
+    lm(F, F->Gzf, 2 * m2, 2 * n, F->A2, 0, Nz, Nz, 1, F->S[l], nullptr, 0, Nz, 0);
+    // per-mode mixing
+    k_mix_fwd<<<gdiv((long long)F->mode_count * w, 256), 256, 0, F->stream>>>(F->S[l], F->bRr[l], F->bRi[l], F->T,
+                                                                               F->mode_count, w, F->Tb);
+    // inverse: z, y (batch z), x (batch z,y)
+    lm(F, F->Gzi, 2 * n, 2 * m2, F->Tb, 0, Nz, Nz, 1, nullptr, F->B3, 0, Nz, 0);
+    lm(F, F->Gyi, 2 * n, 2 * m2, F->B3, (long long)2 * m2 * m * w, m * w, m * w, n, nullptr, F->B2,
+       (long long)2 * n * m * w, m * w, 0);
+    lm(F, F->Gxi, n, 2 * m, F->B2, (long long)2 * m * w, w, w, n * n, F->B1, nullptr, (long long)n * w, w, 0);
+    // pointwise path, bias, residual spectral part, activation (the last layer is linear)
+    const bool last = l == c.layers - 1;
+    cm(F, v, w, w, F->bWT[l], w, th + F->o_b[l], F->B1, w, nullptr, F->pre[l], last ? nullptr : F->v[l + 1], w, 0);
+  }
+  const u16* vL = F->pre[c.layers - 1];  // v_L = pre_{L-1}
+  cm(F, vL, w, w, F->bP1T, h, th + F->o_c1, nullptr, 0, nullptr, F->hpre, F->hact, h, 0);
+  cm(F, F->hact, h, h, F->bP2T, c.cout, th + F->o_c2, nullptr, 0, F->outf, nullptr, nullptr, c.cout, 0);
+  (void)P;
+}
+
+// backward pass; the loss gradient is in F->douthb (bf16 [P][coutp]) and F->dvf2 (f32 [P][cout])
+static void backward(pf_fno* F) {
+  const pf_fno_config& c = F->cfg;
+  const int n = c.n, w = c.width, m = c.modes, m2 = 2 * m, h = c.hidden, co = c.cout;
+  const long long P = F->P;
+  float* g = F->gr;
+  // projection: out = hact P2 + c2
+  wgrad(F, F->hact, h, h, F->dvf2, co, co, g + F->o_P2, g + F->o_c2);
+  cm(F, F->douthb, F->coutp, F->coutp, F->bP2, h, nullptr, nullptr, 0, F->dhf, nullptr, nullptr, h, 0);
+  k_gelu_bwd<<<gdiv(P * h, 256), 256, 0, F->stream>>>(F->dhf, F->hpre, F->dhf, F->dhb, P * h, 0);
+  wgrad(F, F->pre[c.layers - 1], w, w, F->dhf, h, h, g + F->o_P1, g + F->o_c1);
+  cm(F, F->dhb, h, h, F->bP1, w, nullptr, nullptr, 0, F->dvf, nullptr, nullptr, w, 0);
+  const int Nz = m2 * m * w;
+  for (int l = c.layers - 1; l >= 0; --l) {
+    const bool last = l == c.layers - 1;
+    k_gelu_bwd<<<gdiv(P * w, 256), 256, 0, F->stream>>>(F->dvf, F->pre[l], F->dpref, F->dpreb, P * w, last ? 1 : 0);
+    wgrad(F, F->v[l], w, w, F->dpref, w, w, g + F->o_W[l], g + F->o_b[l]);
+    // pointwise data gradient
+    cm(F, F->dpreb, w, w, F->bW[l], w, nullptr, nullptr, 0, F->dvf, nullptr, nullptr, w, 0);
+    // spectral path: transposes of the inverse stages
+    lm(F, F->GxiT, 2 * m, n, F->dpreb, (long long)n * w, w, w, n * n, nullptr, F->B2, (long long)2 * m * w, w, 0);
+    lm(F, F->GyiT, 2 * m2, 2 * n, F->B2, (long long)2 * n * m * w, m * w, m * w, n, nullptr, F->B3,
+       (long long)2 * m2 * m * w, m * w, 0);
+    lm(F, F->GziT, 2 * m2, 2 * n, F->B3, 0, Nz, Nz, 1, F->dT, nullptr, 0, Nz, 0);
+    k_mix_bwd_w<<<gdiv((long long)F->mode_count * w * w, 256), 256, 0, F->stream>>>(
+        F->S[l], F->dT, g + F->o_Rr[l], g + F->o_Ri[l], F->mode_count, w);
+    k_mix_bwd_data<<<gdiv((long long)F->mode_count * w, 256), 256, 0, F->stream>>>(F->dT, F->bRr[l], F->bRi[l],
+                                                                                   F->dSb, F->mode_count, w);
+    // transposes of the forward stages: z, y (batch z), x (batch z,y); accumulate into dv
+    lm(F, F->GzfT, 2 * n, 2 * m2, F->dSb, 0, Nz, Nz, 1, nullptr, F->A2, 0, Nz, 0);
+    lm(F, F->GyfT, 2 * n, 2 * m2, F->A2, (long long)2 * m2 * m * w, m * w, m * w, n, nullptr, F->A1,
+       (long long)2 * n * m * w, m * w, 0);
+    lm(F, F->GxfT, n, 2 * m, F->A1, (long long)2 * m * w, w, w, n * n, F->dvf, nullptr, (long long)n * w, w, 1);
+  }
+  // lift: v0 = x W_lift + b_lift
+  wgrad(F, F->xin, F->cinp, c.cin, F->dvf, w, w, g + F->o_Wl, g + F->o_bl);
+}
+
+extern "C" {
+
+pf_status pf_fno_create(const pf_fno_config* cfg, void* stream, pf_fno** out) {
+  if (!cfg || !out) return PF_ERR_ARG;
+  *out = nullptr;
+  const pf_fno_config c = *cfg;
+  if (c.n < 8 || c.n > 256 || c.n % 8 || c.width < 4 || c.width > 128 || c.width % 4 || c.modes < 2 ||
+      c.modes % 2 || 2 * c.modes > c.n || c.layers < 1 || c.layers > 8 || c.hidden < 8 || c.hidden > 128 || c.hidden % 8 ||
+      c.cin < 1 || c.cin > 8 || c.cout < 1 || c.cout > 8)
+    return PF_ERR_ARG;
+  pf_fno* F = new (std::nothrow) pf_fno();
+  if (!F) return PF_ERR_OOM;
+  F->cfg = c;
+  F->stream = (hipStream_t)stream;
+  F->P = (long long)c.n * c.n * c.n;
+  const int w = c.width, m = c.modes, m2 = 2 * m, h = c.hidden, n = c.n;
+  F->mode_count = m2 * m2 * m;
+  // parameter layout (same order as the oracle)
+  long long off = 0;
+  F->o_Wl = off; off += (long long)c.cin * w;
+  F->o_bl = off; off += w;
+  for (int l = 0; l < c.layers; ++l) {
+    F->o_Rr.push_back(off); off += (long long)F->mode_count * w * w;
+    F->o_Ri.push_back(off); off += (long long)F->mode_count * w * w;
+    F->o_W.push_back(off); off += (long long)w * w;
+    F->o_b.push_back(off); off += w;
+  }
+  F->o_P1 = off; off += (long long)w * h;
+  F->o_c1 = off; off += h;
+  F->o_P2 = off; off += (long long)h * c.cout;
+  F->o_c2 = off; off += c.cout;
+  F->nparams = off;
+  const long long P = F->P;
+  pf_status s = PF_OK;
+  auto A = [&](void** p, size_t b) {
+    if (s == PF_OK) s = falloc(F, p, b);
+  };
+  A((void**)&F->th, 4 * off);
+  A((void**)&F->gr, 4 * off);
+  A((void**)&F->am, 4 * off);
+  A((void**)&F->av, 4 * off);
+  A((void**)&F->bWliftT, 2 * w * F->cinp);
+  F->bWT.resize(c.layers);
+  F->bW.resize(c.layers);
+  F->bRr.resize(c.layers);
+  F->bRi.resize(c.layers);
+  for (int l = 0; l < c.layers; ++l) {
+    A((void**)&F->bWT[l], 2 * w * w);
+    A((void**)&F->bW[l], 2 * w * w);
+    A((void**)&F->bRr[l], 2 * (size_t)F->mode_count * w * w);
+    A((void**)&F->bRi[l], 2 * (size_t)F->mode_count * w * w);
+  }
+  A((void**)&F->bP1T, 2 * h * w);
+  A((void**)&F->bP1, 2 * w * h);
+  A((void**)&F->bP2T, 2 * c.cout * h);
+  A((void**)&F->bP2, 2 * h * F->coutp);
+  A((void**)&F->scale, 4 * 8);
+  A((void**)&F->xin, 2 * P * F->cinp);
+  F->v.resize(c.layers + 1);
+  F->pre.resize(c.layers);
+  F->S.resize(c.layers);
+  for (int l = 0; l <= c.layers; ++l) A((void**)&F->v[l], 2 * P * w);
+  const size_t spec = (size_t)2 * F->mode_count * w;
+  for (int l = 0; l < c.layers; ++l) {
+    A((void**)&F->pre[l], 2 * P * w);
+    A((void**)&F->S[l], 4 * spec);
+  }
+  A((void**)&F->hpre, 2 * P * h);
+  A((void**)&F->hact, 2 * P * h);
+  const size_t a1 = (size_t)n * n * 2 * m * w, a2 = (size_t)n * 2 * m2 * m * w, b2 = (size_t)n * 2 * n * m * w;
+  A((void**)&F->A1, 2 * std::max(a1, b2));
+  A((void**)&F->A2, 2 * std::max(a2, (size_t)2 * n * m2 * m * w));
+  A((void**)&F->A3, 2 * spec);
+  A((void**)&F->Tb, 2 * spec);
+  A((void**)&F->T, 4 * spec);
+  A((void**)&F->B3, 2 * std::max((size_t)2 * n * m2 * m * w, a2));
+  A((void**)&F->B2, 2 * std::max(b2, a1));
+  A((void**)&F->B1, 4 * P * w);
+  A((void**)&F->outf, 4 * P * c.cout);
+  A((void**)&F->dvf, 4 * P * w);
+  A((void**)&F->dvf2, 4 * P * c.cout);
+  A((void**)&F->dpref, 4 * P * w);
+  A((void**)&F->dT, 4 * spec);
+  A((void**)&F->dhf, 4 * P * h);
+  A((void**)&F->dhb, 2 * P * h);
+  A((void**)&F->dpreb, 2 * P * w);
+  A((void**)&F->douthb, 2 * P * F->coutp);
+  A((void**)&F->dSb, 2 * spec);
+  const int nb = (int)gdiv(P, 2048);
+  F->part_elems = (long long)nb * (std::max(w, h) + 1) * std::max(w, h);
+  A((void**)&F->part, 4 * F->part_elems);
+  A((void**)&F->dpart, 8 * (size_t)gdiv(P, 256));
+  A((void**)&F->dsum, 8);
+  if (s == PF_OK && hipHostMalloc((void**)&F->hsum, 8, 0) != hipSuccess) s = PF_ERR_OOM;
+  if (s == PF_OK) {
+    std::vector<std::vector<float>> G;
+    build_dft(n, m, G);
+    const int R[6] = {2 * m, 2 * m2, 2 * m2, n, 2 * n, 2 * n};
+    const int K[6] = {n, 2 * n, 2 * n, 2 * m, 2 * m2, 2 * m2};
+    u16** dst[6] = {&F->Gxf, &F->Gyf, &F->Gzf, &F->Gxi, &F->Gyi, &F->Gzi};
+    u16** dstT[6] = {&F->GxfT, &F->GyfT, &F->GzfT, &F->GxiT, &F->GyiT, &F->GziT};
+    for (int i = 0; i < 6 && s == PF_OK; ++i) {
+      s = upload_bf16(F, G[i], dst[i]);
+      if (s == PF_OK) s = upload_bf16(F, transpose(G[i], R[i], K[i]), dstT[i]);
+    }
+  }
+  if (s == PF_OK) {
+    std::vector<float> one(8, 1.0f);
+    if (hipMemcpy(F->scale, one.data(), 32, hipMemcpyHostToDevice) != hipSuccess) s = PF_ERR_HIP;
+    if (hipMemset(F->th, 0, 4 * off) != hipSuccess || hipMemset(F->gr, 0, 4 * off) != hipSuccess ||
+        hipMemset(F->am, 0, 4 * off) != hipSuccess || hipMemset(F->av, 0, 4 * off) != hipSuccess)
+      s = PF_ERR_HIP;
+  }
+  if (s != PF_OK) {
+    pf_fno_destroy(F);
+    return s;
+  }
+  *out = F;
+  return PF_OK;
+}
+
+void pf_fno_destroy(pf_fno* F) {
+  if (!F) return;
+  if (F->stream) hipStreamSynchronize(F->stream);
+  for (void* p : F->allocs) hipFree(p);
+  if (F->hsum) hipHostFree(F->hsum);
+  delete F;
+}
+
+int64_t pf_fno_num_params(const pf_fno* F) { return F ? F->nparams : 0; }
+
+pf_status pf_fno_set_params(pf_fno* F, const float* host) {
+  if (!F || !host) return PF_ERR_ARG;
+  FH(hipMemcpyAsync(F->th, host, 4 * F->nparams, hipMemcpyHostToDevice, F->stream));
+  refresh(F);
+  FH(hipMemsetAsync(F->am, 0, 4 * F->nparams, F->stream));
+  FH(hipMemsetAsync(F->av, 0, 4 * F->nparams, F->stream));
+  FH(hipMemsetAsync(F->gr, 0, 4 * F->nparams, F->stream));
+  F->adam_t = 0;
+  FH(hipStreamSynchronize(F->stream));
+  return PF_OK;
+}
+
+pf_status pf_fno_get_params(pf_fno* F, float* host) {
+  if (!F || !host) return PF_ERR_ARG;
+  FH(hipMemcpyAsync(host, F->th, 4 * F->nparams, hipMemcpyDeviceToHost, F->stream));
+  FH(hipStreamSynchronize(F->stream));
+  return PF_OK;
+}
+
+pf_status pf_fno_get_grad(pf_fno* F, float* host) {
+  if (!F || !host) return PF_ERR_ARG;
+  FH(hipMemcpyAsync(host, F->gr, 4 * F->nparams, hipMemcpyDeviceToHost, F->stream));
+  FH(hipStreamSynchronize(F->stream));
+  return PF_OK;
+}
+
+pf_status pf_fno_zero_grad(pf_fno* F) {
+  if (!F) return PF_ERR_ARG;
+  FH(hipMemsetAsync(F->gr, 0, 4 * F->nparams, F->stream));
+  return PF_OK;
+}
+
+pf_status pf_fno_set_scale(pf_fno* F, const float* host_scale) {
+  if (!F || !host_scale) return PF_ERR_ARG;
+  FH(hipMemcpyAsync(F->scale, host_scale, 4 * F->cfg.cout, hipMemcpyHostToDevice, F->stream));
+  FH(hipStreamSynchronize(F->stream));
+  return PF_OK;
+}
+
+pf_status pf_fno_forward(pf_fno* F, const float* x, float* out) {
+  if (!F || !x || !out) return PF_ERR_ARG;
+  k_pack_input<float><<<gdiv(F->P, 256), 256, 0, F->stream>>>(x, F->P, F->cfg.cin, F->cinp, F->xin);
+  forward(F);
+  FH(hipMemcpyAsync(out, F->outf, 4 * F->P * F->cfg.cout, hipMemcpyDeviceToDevice, F->stream));
+  FH(hipGetLastError());
+  FH(hipStreamSynchronize(F->stream));
+  return PF_OK;
+}
+
+pf_status pf_fno_grad(pf_fno* F, const float* x, const float* y, double* loss) {
+  if (!F || !x || !y) return PF_ERR_ARG;
+  k_pack_input<float><<<gdiv(F->P, 256), 256, 0, F->stream>>>(x, F->P, F->cfg.cin, F->cinp, F->xin);
+  forward(F);
+  const unsigned nb = gdiv(F->P, 256);
+  k_loss<<<nb, 256, 0, F->stream>>>(F->outf, x, y, F->scale, F->P, F->cfg.cout, F->coutp, F->dvf2, F->douthb,
+                                    F->dpart);
+  k_sum_d<<<1, 256, 0, F->stream>>>(F->dpart, (int)nb, F->dsum);
+  backward(F);
+  FH(hipMemcpyAsync(F->hsum, F->dsum, 8, hipMemcpyDeviceToHost, F->stream));
+  FH(hipGetLastError());
+  FH(hipStreamSynchronize(F->stream));
+  if (loss) *loss = F->hsum[0] / ((double)F->P * F->cfg.cout);
+  return PF_OK;
+}
+
+pf_status pf_fno_adam_step(pf_fno* F, float lr, float beta1, float beta2, float eps, float grad_scale) {
+  if (!F) return PF_ERR_ARG;
+  F->adam_t += 1;
+  const float c1 = 1.f - powf(beta1, (float)F->adam_t), c2 = 1.f - powf(beta2, (float)F->adam_t);
+  k_adam<<<gdiv(F->nparams, 256), 256, 0, F->stream>>>(F->th, F->am, F->av, F->gr, F->nparams, lr, beta1, beta2,
+                                                       eps, grad_scale, c1, c2);
+  refresh(F);
+  FH(hipGetLastError());
+  return PF_OK;
+}
+
+pf_status pf_fno_apply(pf_fno* F, const double* state, double* next) {
+  if (!F || !state || !next || F->cfg.cin != F->cfg.cout) return PF_ERR_ARG;
+  k_pack_input<double><<<gdiv(F->P, 256), 256, 0, F->stream>>>(state, F->P, F->cfg.cin, F->cinp, F->xin);
+  forward(F);
+  const unsigned nb = gdiv(F->P, 256);
+  k_apply<<<nb, 256, 0, F->stream>>>(state, F->outf, F->scale, F->P, F->cfg.cout, next, F->dpart);
+  k_sum_d<<<1, 256, 0, F->stream>>>(F->dpart, (int)nb, F->dsum);
+  k_shift<<<nb, 256, 0, F->stream>>>(next, F->P, F->dsum);
+  FH(hipGetLastError());
+  FH(hipStreamSynchronize(F->stream));
+  return PF_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,91 @@
+"""FNO surrogate kernels (BF16 MFMA, FP32 accumulate) against the FP64 oracle:
+forward output and every parameter gradient, bound 3e-2 relative L2 (BF16
+activations and weights carry ~4e-3 relative rounding per value)."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import fno as of
+
+pytestmark = pytest.mark.gpu
+BOUND = 3e-2
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def _flat(net, p):
+    return np.concatenate([p[k].ravel() for k in net.param_shapes()]).astype(np.float32)
+
+
+def _unflat(net, v):
+    out, o = {}, 0
+    for k, s in net.param_shapes().items():
+        sz = int(np.prod(s))
+        out[k] = v[o:o + sz].reshape(s)
+        o += sz
+    return out
+
+
+@pytest.mark.parametrize("n,w,m,L,h", [(8, 4, 2, 2, 8), (16, 8, 4, 2, 16), (32, 32, 12, 4, 128)])
+def test_fno_forward_and_gradients_match_oracle(n, w, m, L, h):
+    import torch
+    from paper_2609_36100_amd import FNO
+    _say("fno", n, w, m, L, h)
+    net = of.FNO(n, width=w, modes=m, layers=L, hidden=h)
+    p = net.init_params(seed=7)
+    rng = np.random.default_rng(8)
+    for k in p:
+        if k.startswith("b") or k.startswith("c"):
+            p[k] = 0.1 * rng.standard_normal(p[k].shape)
+    # bf16-representable parameters and inputs so both sides start from the same values
+    to_bf = lambda a: torch.from_numpy(np.asarray(a, np.float32)).to(torch.bfloat16).to(torch.float64).numpy()
+    p = {k: to_bf(v) for k, v in p.items()}
+    x = to_bf(rng.uniform(0, 1, (n, n, n, 4)))
+    tgt = rng.standard_normal((n, n, n, 4)) * 0.5
+    out, tape = net.forward(p, x, keep=True)
+    loss, dout = of.mse_loss(out, tgt)
+    g = net.backward(p, tape, dout)
+    with FNO(n, width=w, modes=m, layers=L, hidden=h) as f:
+        f.set_params(_flat(net, p))
+        xt = torch.from_numpy(np.ascontiguousarray(np.moveaxis(x, -1, 0))).float().cuda()
+        yt = xt + torch.from_numpy(np.ascontiguousarray(np.moveaxis(tgt, -1, 0))).float().cuda()
+        gout = f.forward(xt).cpu().numpy().reshape(n, n, n, 4)
+        rel_out = np.linalg.norm(gout - out) / np.linalg.norm(out)
+        f.zero_grad()
+        gl = f.grad(xt, yt)
+        gg = _unflat(net, f.get_grad().astype(np.float64))
+    print("forward rel", rel_out, "loss", gl, loss, flush=True)
+    assert rel_out < BOUND
+    assert abs(gl - loss) < BOUND * loss
+    worst = {}
+    for k in g:
+        r = np.linalg.norm(gg[k] - g[k]) / max(np.linalg.norm(g[k]), 1e-30)
+        worst[k] = r
+    print("grad rel", {k: "%.2e" % v for k, v in worst.items()}, flush=True)
+    for k, r in worst.items():
+        assert r < BOUND, (k, r)
+
+
+def test_fno_adam_reduces_loss():
+    import torch
+    from paper_2609_36100_amd import FNO
+    _say("fno adam")
+    n, w, m, L, h = 16, 8, 4, 2, 16
+    net = of.FNO(n, width=w, modes=m, layers=L, hidden=h)
+    p = net.init_params(seed=1)
+    rng = np.random.default_rng(2)
+    x = torch.from_numpy(rng.uniform(0, 1, (4, n, n, n)).astype(np.float32)).cuda()
+    y = x + 0.1 * torch.sin(3 * x)
+    with FNO(n, width=w, modes=m, layers=L, hidden=h) as f:
+        f.set_params(_flat(net, p))
+        losses = []
+        for it in range(60):
+            f.zero_grad()
+            losses.append(f.grad(x, y))
+            f.adam_step(3e-3)
+    print("losses", losses[0], losses[-1], flush=True)
+    assert losses[-1] < 0.2 * losses[0]
