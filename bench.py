@@ -38,6 +38,27 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
+COUNTERS_MD = os.path.join(ROOT, "profiles", "ark4_stage_cycle_512_hbm_counters.md")
+
+
+def measured_traffic():
+    """HBM bytes per launch from the committed FETCH_SIZE / WRITE_SIZE summary,
+    or None once the kernel sources differ from those the counters were taken on."""
+    import hashlib
+    try:
+        text = open(COUNTERS_MD).read()
+        blob = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
+        h = hashlib.sha256()
+        for f in blob["sources"]:
+            with open(os.path.join(ROOT, f), "rb") as fh:
+                h.update(fh.read())
+        if h.hexdigest()[:16] != blob["sources_sha256"]:
+            return None
+        return blob["traffic"]
+    except (OSError, IndexError, ValueError, KeyError):
+        return None
+
+
 def kernel_table(rep):
     out = {}
     for name, (ms, n, b) in rep.items():
@@ -298,8 +319,15 @@ def main():
     kt = r64["kernels"]
     dom = max(kt, key=lambda k: kt[k]["total_ms"])
     d = kt[dom]
+    tr = measured_traffic()
+    traffic = None
+    if tr is not None and args.n == 512 and ("%s/f64" % dom) in tr:
+        traffic = tr["%s/f64" % dom]
     roofline = dict(bound="hbm", kernel=dom, achieved=d["gbs"], peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=d["frac"], traffic=None)
+                    frac=d["frac"], traffic=traffic,
+                    traffic_note="HBM bytes per launch from rocprofv3 FETCH_SIZE x2 + WRITE_SIZE x1 "
+                                 "(copy-kernel calibration); algorithmic bytes per launch %.0f"
+                                 % d["bytes_per_launch"])
     cpu = None
     if not args.skip_cpu:
         log("CPU oracle sample")
