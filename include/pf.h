@@ -268,6 +268,10 @@ pf_status pf_fno_set_params(pf_fno* f, const float* host_params);
 pf_status pf_fno_get_params(pf_fno* f, float* host_params);
 /* per-channel output scale (cout host floats); the target is (y - x) / scale */
 pf_status pf_fno_set_scale(pf_fno* f, const float* host_scale);
+/* per-channel input normalisation (cin host floats each): the network sees
+ * (x - shift) / scale, formed before rounding to bf16 (default 0 and 1);
+ * PF_ERR_ARG for a scale that is not positive and finite */
+pf_status pf_fno_set_input_norm(pf_fno* f, const float* host_shift, const float* host_scale);
 /* network output for x (device float32 [cin][n^3]) into out (device float32
  * [n^3][cout], point-major) */
 pf_status pf_fno_forward(pf_fno* f, const float* x, float* out);
@@ -280,8 +284,39 @@ pf_status pf_fno_zero_grad(pf_fno* f);
 pf_status pf_fno_adam_step(pf_fno* f, float lr, float beta1, float beta2, float eps, float grad_scale);
 /* surrogate advance: next = state + scale * net(state), then the mean of c is
  * restored (the composition is conserved); state / next device float64
- * [cin][n^3] (cin == cout) */
+ * [cin][n^3] (cin == cout); next may equal state */
 pf_status pf_fno_apply(pf_fno* f, const double* state, double* next);
+
+/* Counters of the checked surrogate advance.  since_check and plain_left are
+ * carried between calls: zero the struct before a member's first call and
+ * pass the same struct to continue it. */
+typedef struct {
+  int32_t surrogate;    /* surrogate advances taken */
+  int32_t checks;       /* surrogate advances recomputed by the plain solver */
+  int32_t fallbacks;    /* checks whose error exceeded the tolerance */
+  int32_t plain;        /* advances run by the plain solver after a fallback */
+  int32_t since_check;  /* surrogate advances since the last check */
+  int32_t plain_left;   /* plain advances still owed after a fallback */
+  double err_last;      /* relative L2 error of c at the last check */
+  double err_max;       /* largest checked error */
+  double ms_surrogate;  /* wall time in surrogate advances */
+  double ms_plain;      /* wall time in checks and plain advances */
+} pf_fno_stats;
+
+/* Advances one member by n_adv intervals of length delta.  Each interval is
+ * one surrogate advance, except that every check_every-th surrogate advance is
+ * also recomputed by the plain solver `plain` (pf_advance over delta from the
+ * same input, with that context's method, tolerances and step control); if
+ * ||c_net - c_plain|| / ||c_plain|| exceeds tol (or is not finite) the plain
+ * result replaces it and the next check_every intervals are run by the plain
+ * solver.  state: device float64 [4][n^3] (c, eta_1..3), updated in place.
+ * plain: a context on the same n^3 grid and device (its state and time are
+ * overwritten; its stream must be ordered with the network's).  Synchronous. */
+pf_status pf_fno_advance(pf_fno* f, pf_ctx* plain, double* state, int32_t n_adv, double delta,
+                         int32_t check_every, double tol, pf_fno_stats* stats);
+/* ||a - b||_2 / ||b||_2 over n device float64 values (||a - b|| if b == 0),
+ * ordered on hip_stream (NULL = default); synchronises that stream. */
+pf_status pf_rel_l2(const double* a, const double* b, int64_t n, void* hip_stream, double* out);
 
 /* Human-readable status name; never NULL. */
 const char* pf_status_string(pf_status s);

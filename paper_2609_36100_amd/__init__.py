@@ -12,9 +12,9 @@ import ctypes
 import numpy as np
 
 from . import _lib
-from ._lib import PFError, Stats, make_params  # noqa: F401
+from ._lib import FnoStats, PFError, Stats, make_params  # noqa: F401
 
-__all__ = ["Solver", "Ensemble", "FNO", "PFError", "make_params", "size_supported"]
+__all__ = ["Solver", "Ensemble", "FNO", "FnoStats", "PFError", "make_params", "rel_l2", "size_supported"]
 
 
 def _torch():
@@ -114,6 +114,18 @@ class Solver:
         _lib.check(_lib.lib().pf_get_state(self._h, c.ctypes.data_as(ctypes.c_void_p),
                                            eta.ctypes.data_as(ctypes.c_void_p), 0), "pf_get_state")
         return c, eta
+
+    def get_state_device(self, out=None):
+        """Real-space state as a device float64 tensor (4, nz, ny, nx)."""
+        torch = _torch()
+        if out is None:
+            out = torch.empty((4,) + self.shape, dtype=torch.float64, device="cuda")
+        _lib.check(_lib.lib().pf_get_state(self._h, _ptr(out[0]), _ptr(out[1]), 1), "pf_get_state")
+        return out
+
+    def set_state_device(self, u, t0=0.0):
+        """Set the state from a device float64 tensor (4, nz, ny, nx)."""
+        _lib.check(_lib.lib().pf_set_state(self._h, _ptr(u[0]), _ptr(u[1]), 1, float(t0)), "pf_set_state")
 
     def get_state_hat(self):
         t = self.kspace_empty()
@@ -310,6 +322,14 @@ class Ensemble:
                    "pf_ensemble_tuning_set")
 
 
+def rel_l2(a, b):
+    """||a - b|| / ||b|| of two device float64 tensors (computed by libpf)."""
+    out = ctypes.c_double()
+    _lib.check(_lib.lib().pf_rel_l2(_ptr(a.contiguous()), _ptr(b.contiguous()), a.numel(), None,
+                                    ctypes.byref(out)), "pf_rel_l2")
+    return out.value
+
+
 class FNO:
     """Fourier neural operator surrogate on the GPU (BF16 MFMA, FP32 master weights).
 
@@ -361,6 +381,14 @@ class FNO:
         sc = np.ascontiguousarray(scale, dtype=np.float32)
         _lib.check(_lib.lib().pf_fno_set_scale(self._h, sc.ctypes.data_as(ctypes.c_void_p)), "pf_fno_set_scale")
 
+    def set_input_norm(self, shift, scale):
+        """The network sees (x - shift) / scale per input channel."""
+        sh = np.ascontiguousarray(shift, dtype=np.float32)
+        sc = np.ascontiguousarray(scale, dtype=np.float32)
+        assert sh.size == self.cin and sc.size == self.cin
+        _lib.check(_lib.lib().pf_fno_set_input_norm(self._h, sh.ctypes.data_as(ctypes.c_void_p),
+                                                    sc.ctypes.data_as(ctypes.c_void_p)), "pf_fno_set_input_norm")
+
     def forward(self, x):
         torch = _torch()
         out = torch.empty((self.n ** 3, self.cout), dtype=torch.float32, device="cuda")
@@ -387,3 +415,16 @@ class FNO:
     def apply(self, state, out):
         """out = state + scale * net(state), mean of c restored (device float64 (cin, n, n, n))."""
         _lib.check(_lib.lib().pf_fno_apply(self._h, _ptr(state), _ptr(out)), "pf_fno_apply")
+
+    def advance(self, plain, state, n_adv, delta, check_every=5, tol=1e-3, stats=None):
+        """Checked surrogate advance of ``state`` (device float64 (4, n, n, n), in place) by
+        ``n_adv`` intervals of ``delta``; ``plain`` is a :class:`Solver` on the same grid that
+        runs the checks and fallbacks.  ``stats`` (an ``FnoStats``) carries the check cadence
+        between calls; returns it."""
+        if stats is None:
+            stats = _lib.FnoStats()
+        assert state.is_contiguous() and state.dtype == _torch().float64
+        _lib.check(_lib.lib().pf_fno_advance(self._h, plain._h, _ptr(state), int(n_adv), float(delta),
+                                             int(check_every), float(tol), ctypes.byref(stats)),
+                   "pf_fno_advance")
+        return stats

@@ -47,6 +47,16 @@ class FnoConfig(ctypes.Structure):
                 ("cout", ctypes.c_int32)]
 
 
+class FnoStats(ctypes.Structure):
+    _fields_ = [("surrogate", ctypes.c_int32), ("checks", ctypes.c_int32), ("fallbacks", ctypes.c_int32),
+                ("plain", ctypes.c_int32), ("since_check", ctypes.c_int32), ("plain_left", ctypes.c_int32),
+                ("err_last", ctypes.c_double), ("err_max", ctypes.c_double),
+                ("ms_surrogate", ctypes.c_double), ("ms_plain", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class Stats(ctypes.Structure):
     _fields_ = [
         ("steps", ctypes.c_int64), ("attempts", ctypes.c_int64),
@@ -131,7 +141,13 @@ _SIGS = {
     "pf_fno_zero_grad": (ctypes.c_int, [ctypes.c_void_p]),
     "pf_fno_adam_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                         ctypes.c_float, ctypes.c_float]),
+    "pf_fno_set_input_norm": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "pf_fno_apply": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "pf_fno_advance": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                                      ctypes.c_double, ctypes.c_int32, ctypes.c_double,
+                                      ctypes.POINTER(FnoStats)]),
+    "pf_rel_l2": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                 ctypes.POINTER(ctypes.c_double)]),
     "pf_profile_enable": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "pf_profile_classes": (ctypes.c_int32, []),
     "pf_profile_name": (ctypes.c_char_p, [ctypes.c_int32]),

@@ -20,6 +20,7 @@
 // refreshes the BF16 working copies.
 #include <hip/hip_runtime.h>
 
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -208,32 +209,107 @@ k_mix_bwd_w(const float* __restrict__ S, const float* __restrict__ dT, float* __
   gRi[id] += sr * ti - si * tr;
 }
 
-// ---- weight gradients: G[k][n] += sum_p A[p][k] D[p][n], bias row k = K ------
-// Partial sums per block over a chunk of points; k_sum_partials adds them.
+// ---- weight gradients on MFMA: G[k][n] += sum_p A[p][k] D[p][n], gb[n] += sum_p D[p][n] ----
+// The reduction runs over points, which are the slow index of both operands,
+// so each block stages WG_PTS points of A (bf16) and D (f32, rounded to bf16)
+// transposed into LDS ([channel][point], padded rows) and every wave feeds
+// 32 of those points to v_mfma_f32_32x32x8bf16_1k for up to four 32 x 32
+// output tiles [t0, t0 + 4) of the ceil(K/32) x ceil(N/32) tile grid.  Each
+// wave writes its partial tiles to part[(block * 4 + wave) * KN + k * N + n]
+// (KN = (K + 1) * N; row k = K holds the bias sums, written by wave 0 when
+// t0 == 0); k_sum_partials adds the sets.  Requires lda % 4 == 0, K <= lda,
+// channels K .. 4 ceil(K/4) of A zero, K, N <= 128, chunk % WG_PTS == 0.
+constexpr int WG_PTS = 128;
+constexpr int WG_LD = WG_PTS + 4;  // bf16 row pitch: 264 B rows keep the 8-byte MFMA reads spread over banks
+
 __global__ void __launch_bounds__(256)
-k_wgrad_partial(const u16* __restrict__ A, int lda, int K, const float* __restrict__ D, int ldd, int N,
-                long long P, int chunk, float* __restrict__ part) {
+k_wgrad_mfma(const u16* __restrict__ A, int lda, int K, const float* __restrict__ D, int ldd, int N, long long P,
+             int chunk, int t0, float* __restrict__ part) {
+  __shared__ __attribute__((aligned(16))) u16 LA[128 * WG_LD];
+  __shared__ __attribute__((aligned(16))) u16 LD[128 * WG_LD];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, lr = lane & 31, lg = lane >> 5;
+  const int Nt = (N + 31) / 32;
+  const int ntiles = min(4, ((K + 31) / 32) * Nt - t0);
   const int KN = (K + 1) * N;
-  const long long p_begin = (long long)blockIdx.x * chunk;
-  const long long p_end = p_begin + chunk < P ? p_begin + chunk : P;
-  for (int e = threadIdx.x; e < KN; e += 256) {
-    const int k = e / N, n = e % N;
-    float s = 0.f;
-    for (long long p = p_begin; p < p_end; ++p) {
-      const float a = k < K ? bf2f(A[p * lda + k]) : 1.0f;
-      s += a * D[p * ldd + n];
+  const int Kq = (K + 3) / 4;  // 4-channel groups of A staged per point
+  for (int e = tid; e < 128 * WG_LD; e += 256) LA[e] = 0, LD[e] = 0;
+  f32x16 acc[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int i = 0; i < 16; ++i) acc[t][i] = 0.0f;
+  float bsum = 0.f;  // bias sum of channel n = tid (tid < N)
+  const long long pb = (long long)blockIdx.x * chunk;
+  const long long pe = pb + chunk < P ? pb + chunk : P;
+  for (long long p0 = pb; p0 < pe; p0 += WG_PTS) {
+    __syncthreads();
+    for (int e = tid; e < WG_PTS * Kq; e += 256) {
+      const int pp = e / Kq, kg = e % Kq;
+      const bf16x4 v = ld4(A + (p0 + pp) * lda + 4 * kg);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) LA[(4 * kg + j) * WG_LD + pp] = (u16)v[j];
     }
-    part[(long long)blockIdx.x * KN + e] = s;
+    for (int e = tid; e < WG_PTS * N; e += 256) {
+      const int pp = e / N, nn = e % N;
+      LD[nn * WG_LD + pp] = f2bf(D[(p0 + pp) * ldd + nn]);
+    }
+    __syncthreads();
+    if (tid < N) {
+      float sacc = 0.f;
+      for (int pp = 0; pp < WG_PTS; pp += 4) {
+        const bf16x4 v = *reinterpret_cast<const bf16x4*>(LD + tid * WG_LD + pp);
+        sacc += (bf2f((u16)v[0]) + bf2f((u16)v[1])) + (bf2f((u16)v[2]) + bf2f((u16)v[3]));
+      }
+      bsum += sacc;
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      if (t >= ntiles) break;
+      const int tile = t0 + t, kt = tile / Nt, nt = tile % Nt;
+      const u16* ra = LA + (kt * 32 + lr) * WG_LD + wave * 32 + lg * 4;
+      const u16* rb = LD + (nt * 32 + lr) * WG_LD + wave * 32 + lg * 4;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const bf16x4 a = *reinterpret_cast<const bf16x4*>(ra + 8 * j);
+        const bf16x4 b = *reinterpret_cast<const bf16x4*>(rb + 8 * j);
+        acc[t] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc[t], 0, 0, 0);
+      }
+    }
+  }
+  float* dst = part + ((long long)blockIdx.x * 4 + wave) * KN;
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    if (t >= ntiles) break;
+    const int tile = t0 + t, kt = tile / Nt, nt = tile % Nt;
+    const int n = nt * 32 + lr;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int k = kt * 32 + 8 * (i >> 2) + 4 * lg + (i & 3);
+      if (k < K && n < N) dst[k * N + n] = acc[t][i];
+    }
+  }
+  if (t0 == 0 && tid < N) {
+    // the bias row: block sum in wave 0's set, zero in the others
+    for (int w = 0; w < 4; ++w) part[((long long)blockIdx.x * 4 + w) * KN + K * N + tid] = w == 0 ? bsum : 0.f;
   }
 }
 
-__global__ void __launch_bounds__(256) k_sum_partials(const float* __restrict__ part, int nb, int KN,
-                                                      float* __restrict__ gW, float* __restrict__ gb, int K, int N) {
+// Adds nsets partial sets into gW / gb, for the entries of tiles [t0, t0 + 4)
+// (and the bias row when t0 == 0).
+__global__ void __launch_bounds__(256) k_sum_partials(const float* __restrict__ part, int nsets, int K, int N,
+                                                      int t0, float* __restrict__ gW, float* __restrict__ gb) {
+  const int KN = (K + 1) * N;
   const int e = blockIdx.x * 256 + threadIdx.x;
   if (e >= KN) return;
-  float s = 0.f;
-  for (int b = 0; b < nb; ++b) s += part[(long long)b * KN + e];
   const int k = e / N, n = e % N;
+  if (k < K) {
+    const int tile = (k / 32) * ((N + 31) / 32) + n / 32;
+    if (tile < t0 || tile >= t0 + 4) return;
+  } else if (t0 != 0) {
+    return;
+  }
+  float s = 0.f;
+  for (int b = 0; b < nsets; ++b) s += part[(long long)b * KN + e];
   if (k < K)
     gW[k * N + n] += s;
   else
@@ -252,13 +328,20 @@ __global__ void __launch_bounds__(256) k_gelu_bwd(const float* __restrict__ dpos
   dpreb[i] = f2bf(g);
 }
 
-// planar f32 [cin][P] (or f64) -> bf16 [P][ld] zero padded
+// per-channel input normalisation (x - shift) * inv, applied before rounding to bf16
+struct InNorm {
+  float shift[8];
+  float inv[8];
+};
+
+// planar f32 [cin][P] (or f64) -> normalised bf16 [P][ld] zero padded
 template <typename TI>
 __global__ void __launch_bounds__(256) k_pack_input(const TI* __restrict__ x, long long P, int cin, int ld,
-                                                    u16* __restrict__ out) {
+                                                    InNorm nm, u16* __restrict__ out) {
   const long long p = blockIdx.x * 256LL + threadIdx.x;
   if (p >= P) return;
-  for (int c = 0; c < ld; ++c) out[p * ld + c] = c < cin ? f2bf((float)x[c * P + p]) : (u16)0;
+  for (int c = 0; c < ld; ++c)
+    out[p * ld + c] = c < cin ? f2bf((float)((x[c * P + p] - (TI)nm.shift[c]) * (TI)nm.inv[c])) : (u16)0;
 }
 
 // loss: out f32 [P][co] vs target (y - x) / scale (planar f32); writes dout
@@ -350,6 +433,31 @@ __global__ void __launch_bounds__(256) k_shift(double* __restrict__ c, long long
   if (p < P) c[p] -= sum[0] / (double)P;
 }
 
+// partial sums of (a - b)^2 and b^2
+__global__ void __launch_bounds__(256) k_rel_l2(const double* __restrict__ a, const double* __restrict__ b,
+                                                long long n, double* __restrict__ part) {
+  __shared__ double sh[2][4];
+  double d2 = 0.0, b2 = 0.0;
+  for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += 256LL * gridDim.x) {
+    const double d = a[i] - b[i];
+    d2 += d * d;
+    b2 += b[i] * b[i];
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    d2 += __shfl_xor(d2, o, 64);
+    b2 += __shfl_xor(b2, o, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    sh[0][threadIdx.x >> 6] = d2;
+    sh[1][threadIdx.x >> 6] = b2;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = sh[0][0] + sh[0][1] + sh[0][2] + sh[0][3];
+    part[2 * blockIdx.x + 1] = sh[1][0] + sh[1][1] + sh[1][2] + sh[1][3];
+  }
+}
+
 }  // namespace
 
 // ---- host side ----------------------------------------------------------------
@@ -371,6 +479,7 @@ struct pf_fno {
   // DFT matrices (forward and inverse stages, and their transposes)
   u16 *Gxf, *Gyf, *Gzf, *Gxi, *Gyi, *Gzi, *GxfT, *GyfT, *GzfT, *GxiT, *GyiT, *GziT;
   float* scale = nullptr;  // output scale per channel
+  InNorm innorm;           // input normalisation (identity by default)
   // activations
   u16* xin = nullptr;
   std::vector<u16*> v, pre;
@@ -386,6 +495,11 @@ struct pf_fno {
   double* dpart = nullptr;
   double* dsum = nullptr;
   double* hsum = nullptr;  // pinned
+  // checked-advance buffers (allocated on first use)
+  double* adv_next = nullptr;
+  double* adv_ref = nullptr;
+  double* l2_part = nullptr;
+  double* l2_host = nullptr;  // pinned
   std::vector<void*> allocs;
 };
 
@@ -475,12 +589,18 @@ static void cm(pf_fno* F, const u16* In, int ldin, int K, const u16* Bt, int N, 
                                                accumulate);
 }
 
+constexpr int kWgradBlocks = 256;  // blocks (point chunks) of one weight-gradient reduction
+
 static void wgrad(pf_fno* F, const u16* A, int lda, int K, const float* D, int ldd, int N, float* gW, float* gb) {
-  const int chunk = 2048;
+  const long long per = (F->P + kWgradBlocks - 1) / kWgradBlocks;
+  const int chunk = (int)((per + WG_PTS - 1) / WG_PTS * WG_PTS);
   const int nb = (int)gdiv(F->P, chunk);
   const int KN = (K + 1) * N;
-  k_wgrad_partial<<<nb, 256, 0, F->stream>>>(A, lda, K, D, ldd, N, F->P, chunk, F->part);
-  k_sum_partials<<<gdiv(KN, 256), 256, 0, F->stream>>>(F->part, nb, KN, gW, gb, K, N);
+  const int tiles = ((K + 31) / 32) * ((N + 31) / 32);
+  for (int t0 = 0; t0 < tiles; t0 += 4) {
+    k_wgrad_mfma<<<nb, 256, 0, F->stream>>>(A, lda, K, D, ldd, N, F->P, chunk, t0, F->part);
+    k_sum_partials<<<gdiv(KN, 256), 256, 0, F->stream>>>(F->part, 4 * nb, K, N, t0, gW, gb);
+  }
 }
 
 // refresh the bf16 working weights from the FP32 master vector
@@ -592,6 +712,7 @@ pf_status pf_fno_create(const pf_fno_config* cfg, void* stream, pf_fno** out) {
   F->cfg = c;
   F->stream = (hipStream_t)stream;
   F->P = (long long)c.n * c.n * c.n;
+  for (int i = 0; i < 8; ++i) F->innorm.shift[i] = 0.f, F->innorm.inv[i] = 1.f;
   const int w = c.width, m = c.modes, m2 = 2 * m, h = c.hidden, n = c.n;
   F->mode_count = m2 * m2 * m;
   // parameter layout (same order as the oracle)
@@ -665,8 +786,7 @@ pf_status pf_fno_create(const pf_fno_config* cfg, void* stream, pf_fno** out) {
   A((void**)&F->dpreb, 2 * P * w);
   A((void**)&F->douthb, 2 * P * F->coutp);
   A((void**)&F->dSb, 2 * spec);
-  const int nb = (int)gdiv(P, 2048);
-  F->part_elems = (long long)nb * (std::max(w, h) + 1) * std::max(w, h);
+  F->part_elems = 4LL * kWgradBlocks * (std::max(std::max(w, h), 8) + 1) * std::max(std::max(w, h), 8);
   A((void**)&F->part, 4 * F->part_elems);
   A((void**)&F->dpart, 8 * (size_t)gdiv(P, 256));
   A((void**)&F->dsum, 8);
@@ -703,6 +823,7 @@ void pf_fno_destroy(pf_fno* F) {
   if (F->stream) hipStreamSynchronize(F->stream);
   for (void* p : F->allocs) hipFree(p);
   if (F->hsum) hipHostFree(F->hsum);
+  if (F->l2_host) hipHostFree(F->l2_host);
   delete F;
 }
 
@@ -747,9 +868,20 @@ pf_status pf_fno_set_scale(pf_fno* F, const float* host_scale) {
   return PF_OK;
 }
 
+pf_status pf_fno_set_input_norm(pf_fno* F, const float* shift, const float* scale) {
+  if (!F || !shift || !scale) return PF_ERR_ARG;
+  for (int c = 0; c < F->cfg.cin; ++c)
+    if (!(scale[c] > 0.f) || !std::isfinite(shift[c]) || !std::isfinite(scale[c])) return PF_ERR_ARG;
+  for (int c = 0; c < 8; ++c) {
+    F->innorm.shift[c] = c < F->cfg.cin ? shift[c] : 0.f;
+    F->innorm.inv[c] = c < F->cfg.cin ? 1.f / scale[c] : 1.f;
+  }
+  return PF_OK;
+}
+
 pf_status pf_fno_forward(pf_fno* F, const float* x, float* out) {
   if (!F || !x || !out) return PF_ERR_ARG;
-  k_pack_input<float><<<gdiv(F->P, 256), 256, 0, F->stream>>>(x, F->P, F->cfg.cin, F->cinp, F->xin);
+  k_pack_input<float><<<gdiv(F->P, 256), 256, 0, F->stream>>>(x, F->P, F->cfg.cin, F->cinp, F->innorm, F->xin);
   forward(F);
   FH(hipMemcpyAsync(out, F->outf, 4 * F->P * F->cfg.cout, hipMemcpyDeviceToDevice, F->stream));
   FH(hipGetLastError());
@@ -759,7 +891,7 @@ pf_status pf_fno_forward(pf_fno* F, const float* x, float* out) {
 
 pf_status pf_fno_grad(pf_fno* F, const float* x, const float* y, double* loss) {
   if (!F || !x || !y) return PF_ERR_ARG;
-  k_pack_input<float><<<gdiv(F->P, 256), 256, 0, F->stream>>>(x, F->P, F->cfg.cin, F->cinp, F->xin);
+  k_pack_input<float><<<gdiv(F->P, 256), 256, 0, F->stream>>>(x, F->P, F->cfg.cin, F->cinp, F->innorm, F->xin);
   forward(F);
   const unsigned nb = gdiv(F->P, 256);
   k_loss<<<nb, 256, 0, F->stream>>>(F->outf, x, y, F->scale, F->P, F->cfg.cout, F->coutp, F->dvf2, F->douthb,
@@ -784,9 +916,43 @@ pf_status pf_fno_adam_step(pf_fno* F, float lr, float beta1, float beta2, float 
   return PF_OK;
 }
 
+static constexpr int kL2Blocks = 512;
+
+// ||a - b|| / ||b|| with caller-provided partials (device) and staging (pinned host)
+static pf_status rel_l2_impl(hipStream_t s, const double* a, const double* b, long long n, double* part,
+                             double* host, double* out) {
+  k_rel_l2<<<kL2Blocks, 256, 0, s>>>(a, b, n, part);
+  FH(hipGetLastError());
+  FH(hipMemcpyAsync(host, part, sizeof(double) * 2 * kL2Blocks, hipMemcpyDeviceToHost, s));
+  FH(hipStreamSynchronize(s));
+  double d2 = 0.0, b2 = 0.0;
+  for (int i = 0; i < kL2Blocks; ++i) {
+    d2 += host[2 * i];
+    b2 += host[2 * i + 1];
+  }
+  *out = b2 > 0.0 ? std::sqrt(d2 / b2) : std::sqrt(d2);
+  return PF_OK;
+}
+
+pf_status pf_rel_l2(const double* a, const double* b, int64_t n, void* stream, double* out) {
+  if (!a || !b || n < 1 || !out) return PF_ERR_ARG;
+  double* part = nullptr;
+  double* host = nullptr;
+  if (hipMalloc((void**)&part, sizeof(double) * 2 * kL2Blocks) != hipSuccess) return PF_ERR_OOM;
+  if (hipHostMalloc((void**)&host, sizeof(double) * 2 * kL2Blocks, 0) != hipSuccess) {
+    hipFree(part);
+    return PF_ERR_OOM;
+  }
+  pf_status st = rel_l2_impl((hipStream_t)stream, a, b, n, part, host, out);
+  hipStreamSynchronize((hipStream_t)stream);
+  hipHostFree(host);
+  hipFree(part);
+  return st;
+}
+
 pf_status pf_fno_apply(pf_fno* F, const double* state, double* next) {
   if (!F || !state || !next || F->cfg.cin != F->cfg.cout) return PF_ERR_ARG;
-  k_pack_input<double><<<gdiv(F->P, 256), 256, 0, F->stream>>>(state, F->P, F->cfg.cin, F->cinp, F->xin);
+  k_pack_input<double><<<gdiv(F->P, 256), 256, 0, F->stream>>>(state, F->P, F->cfg.cin, F->cinp, F->innorm, F->xin);
   forward(F);
   const unsigned nb = gdiv(F->P, 256);
   k_apply<<<nb, 256, 0, F->stream>>>(state, F->outf, F->scale, F->P, F->cfg.cout, next, F->dpart);
@@ -794,6 +960,73 @@ pf_status pf_fno_apply(pf_fno* F, const double* state, double* next) {
   k_shift<<<nb, 256, 0, F->stream>>>(next, F->P, F->dsum);
   FH(hipGetLastError());
   FH(hipStreamSynchronize(F->stream));
+  return PF_OK;
+}
+
+// one plain-solver interval: out = plain(state) over [0, delta]
+static pf_status plain_interval(pf_ctx* plain, const double* in, double* out, long long P, double delta) {
+  pf_status s = pf_set_state(plain, in, in + P, 1, 0.0);
+  if (s != PF_OK) return s;
+  s = pf_advance(plain, delta, nullptr);
+  if (s != PF_OK) return s;
+  return pf_get_state(plain, out, out + P, 1);
+}
+
+pf_status pf_fno_advance(pf_fno* F, pf_ctx* plain, double* state, int32_t n_adv, double delta,
+                         int32_t check_every, double tol, pf_fno_stats* st) {
+  if (!F || !plain || !state || !st || n_adv < 0 || !(delta > 0.0) || check_every < 1 || !(tol >= 0.0) ||
+      F->cfg.cin != 4 || F->cfg.cout != 4)
+    return PF_ERR_ARG;
+  const long long P = F->P;
+  const size_t bytes = sizeof(double) * 4 * P;
+  if (!F->adv_next) {
+    pf_status s = falloc(F, (void**)&F->adv_next, bytes);
+    if (s == PF_OK) s = falloc(F, (void**)&F->adv_ref, bytes);
+    if (s == PF_OK) s = falloc(F, (void**)&F->l2_part, sizeof(double) * 2 * kL2Blocks);
+    if (s == PF_OK && hipHostMalloc((void**)&F->l2_host, sizeof(double) * 2 * kL2Blocks, 0) != hipSuccess)
+      s = PF_ERR_OOM;
+    if (s != PF_OK) return s;
+  }
+  using clk = std::chrono::steady_clock;
+  auto ms_since = [](clk::time_point t0) {
+    return std::chrono::duration<double, std::milli>(clk::now() - t0).count();
+  };
+  for (int32_t a = 0; a < n_adv; ++a) {
+    if (st->plain_left > 0) {
+      const auto t0 = clk::now();
+      pf_status s = plain_interval(plain, state, state, P, delta);
+      st->ms_plain += ms_since(t0);
+      if (s != PF_OK) return s;
+      st->plain += 1;
+      st->plain_left -= 1;
+      continue;
+    }
+    const bool check = st->since_check + 1 >= check_every;
+    auto t0 = clk::now();
+    pf_status s = pf_fno_apply(F, state, check ? F->adv_next : state);
+    st->ms_surrogate += ms_since(t0);
+    if (s != PF_OK) return s;
+    st->surrogate += 1;
+    st->since_check += 1;
+    if (!check) continue;
+    st->since_check = 0;
+    st->checks += 1;
+    t0 = clk::now();
+    s = plain_interval(plain, state, F->adv_ref, P, delta);
+    double err = 0.0;
+    if (s == PF_OK) s = rel_l2_impl(F->stream, F->adv_next, F->adv_ref, P, F->l2_part, F->l2_host, &err);
+    if (s != PF_OK) return s;
+    st->err_last = err;
+    if (!(err <= st->err_max)) st->err_max = err;
+    const bool fail = !(err <= tol);
+    if (fail) {
+      st->fallbacks += 1;
+      st->plain_left = check_every;
+    }
+    FH(hipMemcpyAsync(state, fail ? F->adv_ref : F->adv_next, bytes, hipMemcpyDeviceToDevice, F->stream));
+    FH(hipStreamSynchronize(F->stream));
+    st->ms_plain += ms_since(t0);
+  }
   return PF_OK;
 }
 

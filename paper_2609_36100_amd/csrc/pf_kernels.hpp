@@ -287,7 +287,7 @@ __device__ inline void body_stage_invz(const StageArgs<TE>& sa, const Geo& g, co
     // combine + solve position by position into LDS (bounded unroll keeps the
     // stage-array loads of a few positions in flight, not all of them)
     __syncthreads();
-#pragma unroll 2
+#pragma unroll 1
     for (int t = 0; t < CG::R0; ++t) {
       const int z = bf + t * CG::TL;
       const long long idx = f * g.fs + ((long long)z * g.ny + y) * g.P + x;

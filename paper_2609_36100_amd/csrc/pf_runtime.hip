@@ -444,7 +444,8 @@ static pf_status stages_and_finalize(pf_ctx* c, double dt, int* n_rhs) {
   fa.atol = c->p.atol;
   fa.sc = 1.0 / std::sqrt((double)c->g.nx * c->g.ny * c->g.nz);
   fa.partial = c->partial;
-  double b_fin = 8.0 * 4 * c->g.nz * (double)c->g.ny * c->g.nxh * 2;  // y read + ynew write (FP64)
+  // y read + ynew write (4 complex FP64 fields each)
+  double b_fin = 2.0 * 4 * c->g.nz * (double)c->g.ny * c->g.nxh * sizeof(cx<double>);
   for (int j = 0; j < tb.s; ++j) {
     const double nv = 4.0 * c->g.nz * (double)c->g.ny * c->g.nxh;
     if (fa.bI[j] != 0.0 || fa.dI[j] != 0.0) b_fin += nv * sizeof(cx<double>);

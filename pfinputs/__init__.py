@@ -190,3 +190,16 @@ def ensemble_members(count=64, base_seed=2000, sizes=(48, 64, 96, 128),
             item.update(c=c, eta=eta, nuclei=nuc)
         out.append(item)
     return out
+
+
+def surrogate_run(r, n=128, base_seed=3000, nuclei=(10, 80)):
+    """Initial condition of training run ``r`` for the learned surrogate: seed
+    ``base_seed + r``, draw order ``c0 ~ U(0.14, 0.18)``, nucleus count in
+    ``nuclei`` (inclusive), then the fields as in :func:`seeded_nuclei`
+    (radius 2..5, spacing 8) -- the ensemble members' distribution at one
+    fixed size."""
+    rng = np.random.Generator(np.random.PCG64(base_seed + r))
+    c0 = float(rng.uniform(0.14, 0.18))
+    k = int(rng.integers(nuclei[0], nuclei[1] + 1))
+    c, eta, nuc = seeded_nuclei(n, None, c0=c0, n_nuclei=k, radius=(2, 5), d_min=8.0, rng=rng)
+    return dict(run=r, n=n, c0=c0, n_nuclei=k, seed=base_seed + r, c=c, eta=eta, nuclei=nuc)

@@ -70,6 +70,48 @@ def test_fno_forward_and_gradients_match_oracle(n, w, m, L, h):
         assert r < BOUND, (k, r)
 
 
+def test_fno_input_normalisation_matches_oracle():
+    """The network sees (x - shift) / scale rounded to bf16: the oracle fed that
+    input gives the same output and gradients; the loss target stays (y - x)."""
+    import torch
+    from paper_2609_36100_amd import FNO, PFError
+    _say("fno input normalisation")
+    n, w, m, L, h = 16, 8, 4, 2, 16
+    net = of.FNO(n, width=w, modes=m, layers=L, hidden=h)
+    p = net.init_params(seed=3)
+    to_bf = lambda a: torch.from_numpy(np.asarray(a, np.float32)).to(torch.bfloat16).to(torch.float64).numpy()
+    p = {k: to_bf(v) for k, v in p.items()}
+    rng = np.random.default_rng(4)
+    shift = np.array([0.16, 0.1, 0.2, 0.05], np.float32)
+    scale = np.array([0.004, 0.3, 0.25, 0.1], np.float32)
+    raw = (shift + scale * rng.standard_normal((n, n, n, 4))).astype(np.float32)
+    xn = (torch.from_numpy(raw) - torch.from_numpy(shift)) * (torch.tensor(1.0, dtype=torch.float32)
+                                                               / torch.from_numpy(scale))
+    x = xn.to(torch.bfloat16).to(torch.float64).numpy()
+    tgt = rng.standard_normal((n, n, n, 4)) * 0.5
+    out, tape = net.forward(p, x, keep=True)
+    loss, dout = of.mse_loss(out, tgt)
+    g = net.backward(p, tape, dout)
+    with FNO(n, width=w, modes=m, layers=L, hidden=h) as f:
+        f.set_params(_flat(net, p))
+        f.set_input_norm(shift, scale)
+        xt = torch.from_numpy(np.ascontiguousarray(np.moveaxis(raw, -1, 0))).cuda()
+        yt = xt + torch.from_numpy(np.ascontiguousarray(np.moveaxis(tgt, -1, 0))).float().cuda()
+        gout = f.forward(xt).cpu().numpy().reshape(n, n, n, 4)
+        f.zero_grad()
+        gl = f.grad(xt, yt)
+        gg = _unflat(net, f.get_grad().astype(np.float64))
+        with pytest.raises(PFError):
+            f.set_input_norm(shift, np.zeros(4, np.float32))
+    rel_out = np.linalg.norm(gout - out) / np.linalg.norm(out)
+    print("forward rel", rel_out, flush=True)
+    assert rel_out < BOUND
+    assert abs(gl - loss) < BOUND * loss
+    for k in g:
+        r = np.linalg.norm(gg[k] - g[k]) / max(np.linalg.norm(g[k]), 1e-30)
+        assert r < BOUND, (k, r)
+
+
 def test_fno_adam_reduces_loss():
     import torch
     from paper_2609_36100_amd import FNO

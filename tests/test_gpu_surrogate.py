@@ -1,0 +1,169 @@
+"""Checked surrogate advance (pf_fno_advance) and the training / gain test of
+the learned surrogate, on the GPU.
+
+The fallback logic is pinned by its two limits: a tolerance no check can meet
+(every checked interval is replaced by the plain solver, then the plain solver
+runs the next intervals, so the result is the plain trajectory) and one every
+check meets (the result is the network applied interval after interval).  The
+training test is the small-grid version of the gain test: a network trained on
+plain-solver trajectories must predict held-out intervals far better than
+both its untrained self and the no-change guess.  Training outcomes are
+stochastic: parity unpinned, bounds stated here.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+N = 32
+DT = 0.05
+DELTA = 0.25          # five fixed ARK4 steps
+NUCLEI = (2, 6)       # what fits at spacing 8 in a 32^3 box
+
+
+def _lib():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2609_36100_amd as pf
+    from paper_2609_36100_amd import surrogate as sg
+    return pf, sg
+
+
+def _state(pf, run=0):
+    import pfinputs
+    ic = pfinputs.surrogate_run(run, N, 3000, NUCLEI)
+    # smooth the sharp nuclei with a few plain steps so every field moves
+    with pf.Solver(N, None, method="ark436l", dt0=DT) as s:
+        s.set_state(ic["c"], ic["eta"])
+        s.advance(0.5)
+        return s.get_state_device().clone()
+
+
+def _small_fno(pf, sg, seed=0, width=8, modes=4, layers=2, hidden=16):
+    f = sg.make_fno(N, width=width, modes=modes, layers=layers, hidden=hidden, seed=seed)
+    f.set_scale(np.full(4, 1e-3, np.float32))
+    return f
+
+
+def test_rel_l2_matches_definition():
+    pf, _ = _lib()
+    g = torch.Generator(device="cpu").manual_seed(5)
+    a = torch.randn(4 * 17 ** 3 + 3, dtype=torch.float64, generator=g)
+    b = torch.randn(a.numel(), dtype=torch.float64, generator=g)
+    want = float(np.linalg.norm((a - b).numpy()) / np.linalg.norm(b.numpy()))
+    got = pf.rel_l2(a.cuda(), b.cuda())
+    assert abs(got - want) <= 1e-13 * want
+    z = torch.zeros(100, dtype=torch.float64)
+    assert pf.rel_l2(a[:100].cuda(), z.cuda()) == pytest.approx(float(np.linalg.norm(a[:100].numpy())), rel=1e-13)
+
+
+def test_fallback_everywhere_gives_the_plain_trajectory():
+    pf, sg = _lib()
+    u0 = _state(pf)
+    f = _small_fno(pf, sg)
+    with pf.Solver(N, None, method="ark436l", dt0=DT) as plain:
+        u = u0.clone()
+        st = f.advance(plain, u, 6, DELTA, check_every=1, tol=0.0)
+    assert (st.surrogate, st.checks, st.fallbacks, st.plain) == (3, 3, 3, 3)
+    assert st.plain_left == 0 and st.since_check == 0
+    assert st.err_max > 0.0
+    with pf.Solver(N, None, method="ark436l", dt0=DT) as ref:
+        ref.set_state_device(u0)
+        for i in range(6):
+            ref.advance((i + 1) * DELTA)
+        want = ref.get_state_device()
+    for fld in range(4):
+        assert pf.rel_l2(u[fld], want[fld]) < 1e-11, fld
+
+
+def test_no_fallback_gives_the_network_trajectory():
+    pf, sg = _lib()
+    u0 = _state(pf)
+    f = _small_fno(pf, sg, seed=1)
+    with pf.Solver(N, None, method="ark436l", dt0=DT) as plain:
+        u = u0.clone()
+        st = f.advance(plain, u, 4, DELTA, check_every=2, tol=1e300)
+    assert (st.surrogate, st.checks, st.fallbacks, st.plain) == (4, 2, 0, 0)
+    assert np.isfinite(st.err_last) and st.err_last > 0.0
+    v = u0.clone()
+    w = torch.empty_like(v)
+    for _ in range(4):
+        f.apply(v, w)
+        v, w = w, v
+    assert torch.equal(u, v)
+    # the mean of c is the input's (composition conserved)
+    assert abs(float(u[0].mean() - u0[0].mean())) < 1e-15
+
+
+def test_check_cadence_carries_between_calls():
+    pf, sg = _lib()
+    u0 = _state(pf)
+    f = _small_fno(pf, sg, seed=2)
+    with pf.Solver(N, None, method="ark436l", dt0=DT) as plain:
+        a = u0.clone()
+        sa = f.advance(plain, a, 7, DELTA, check_every=3, tol=0.0)
+        b = u0.clone()
+        sb = pf.FnoStats()
+        for k in (2, 1, 4):
+            f.advance(plain, b, k, DELTA, check_every=3, tol=0.0, stats=sb)
+    for k in ("surrogate", "checks", "fallbacks", "plain", "since_check", "plain_left"):
+        assert getattr(sa, k) == getattr(sb, k), k
+    assert (sa.surrogate, sa.fallbacks, sa.plain) == (4, 1, 3)
+    assert torch.equal(a, b)
+
+
+def test_rejects_bad_arguments():
+    pf, sg = _lib()
+    f = _small_fno(pf, sg)
+    u = torch.zeros((4, N, N, N), dtype=torch.float64, device="cuda")
+    with pf.Solver(N, None, method="ark436l", dt0=DT) as plain:
+        for kw in (dict(delta=0.0), dict(check_every=0), dict(tol=-1.0)):
+            args = dict(delta=DELTA, check_every=5, tol=1e-3)
+            args.update(kw)
+            with pytest.raises(pf.PFError):
+                f.advance(plain, u, 1, **args)
+
+
+def test_trained_network_beats_untrained_and_no_change():
+    """Small-grid gain test: train on plain trajectories of 12 runs, score the
+    training pairs and 4 held-out runs (increments predicted per channel, and c
+    after one advance against the no-change guess).  At 32^3 with 2-6 nuclei
+    per run the held-out generalisation is limited (measured: c increment
+    error ~0.15 on training pairs, ~0.5 held out); the bounds leave margin."""
+    pf, sg = _lib()
+    import time
+    snaps, _ = sg.generate_snapshots(N, runs=16, snapshots=12, delta=DELTA, base_seed=3000, nuclei=NUCLEI)
+    train = range(12)
+    held = range(12, 16)
+    scale = sg.increment_scale(snaps, 12)
+    norm = sg.state_norm(snaps, 12)
+    f = sg.make_fno(N, width=16, modes=6, layers=3, hidden=32, seed=0, scale=scale, norm=norm)
+    e0, keep, inc0 = sg.validate(f, snaps, held)
+    t0 = time.perf_counter()
+    hist = sg.train(f, snaps, 12, epochs=40, lr=3e-3, batch=4, seed=0)
+    wall = time.perf_counter() - t0
+    _, _, inc_tr = sg.validate(f, snaps, train)
+    e1, _, inc1 = sg.validate(f, snaps, held)
+    print("\nloss %.3e -> %.3e in %.1f s; increment error per channel: train %s, held out %s (untrained %s); "
+          "held-out rel-L2(c): trained %.3e, no change %.3e"
+          % (hist[0], hist[-1], wall, np.round(inc_tr, 3), np.round(inc1, 3), np.round(inc0, 3), e1.mean(),
+             keep.mean()))
+    assert hist[-1] < 0.1 * hist[0]
+    assert np.all(inc_tr < 0.3)
+    assert np.all(inc1 < 0.8) and np.all(inc1 < inc0)
+    assert e1.mean() < 0.75 * keep.mean()
+    # the checked advance on a held-out run: every interval is accounted for and
+    # the result stays near the plain solver's
+    u0 = snaps[15, 0].double().contiguous()
+    with pf.Solver(N, None, method="ark436l", dt0=DT) as plain:
+        u = u0.clone()
+        st = f.advance(plain, u, 10, DELTA, check_every=5, tol=1e-3)
+        plain.set_state_device(u0)
+        plain.advance(10 * DELTA)
+        want = plain.get_state_device()
+    err = pf.rel_l2(u[0], want[0])
+    print("checked advance: %s; final rel-L2(c) vs plain %.3e" % (st.as_dict(), err))
+    assert st.surrogate + st.plain == 10 and st.checks == st.surrogate // 5
+    assert err < 2e-2

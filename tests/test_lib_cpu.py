@@ -44,10 +44,11 @@ def test_host_only_entry_points():
 
 
 def test_params_struct_matches_header_layout():
-    """sizeof(pf_params) / sizeof(pf_stats) seen by ctypes equal the C compiler's."""
+    """sizeof of the ABI structs seen by ctypes equal the C compiler's."""
     from paper_2609_36100_amd import _lib
     src = ('#include "pf.h"\n#include <stdio.h>\n'
-           'int main(){printf("%zu %zu\\n", sizeof(pf_params), sizeof(pf_stats));return 0;}\n')
+           'int main(){printf("%zu %zu %zu %zu\\n", sizeof(pf_params), sizeof(pf_stats), sizeof(pf_fno_config),'
+           ' sizeof(pf_fno_stats));return 0;}\n')
     exe = "/tmp/pf_sizeof_check"
     r = subprocess.run(["gcc", "-x", "c", "-I", os.path.join(ROOT, "include"), "-o", exe, "-"],
                        input=src, text=True, capture_output=True)
@@ -55,6 +56,8 @@ def test_params_struct_matches_header_layout():
     out = subprocess.run([exe], capture_output=True, text=True).stdout.split()
     assert int(out[0]) == ctypes.sizeof(_lib.Params)
     assert int(out[1]) == ctypes.sizeof(_lib.Stats)
+    assert int(out[2]) == ctypes.sizeof(_lib.FnoConfig)
+    assert int(out[3]) == ctypes.sizeof(_lib.FnoStats)
 
 
 def test_fft_building_blocks_on_host():
