@@ -75,6 +75,7 @@ def run_solver(torch, n, c, eta, precision, steps, warmup, dt):
     s = Solver(n, None, method="ark436l", precision=precision, dt0=dt)
     s.set_state(c, eta)
     tuning = s.autotune(3)          # tile plans, chosen before the timed region
+    log("%s tile plans: %s" % (precision, {k: (v["variant"], [round(x, 3) for x in v["ms"]]) for k, v in tuning.items()}))
     for _ in range(warmup):
         acc, _, _ = s.step(dt)
         assert acc
@@ -94,7 +95,8 @@ def run_solver(torch, n, c, eta, precision, steps, warmup, dt):
     stages = 6 * steps
     return dict(value=n ** 3 * stages / wall / 1e6, ms_per_step=1e3 * wall / steps,
                 kernels=kernel_table(rep), n_rhs=st["n_rhs"], err_last=err,
-                tuning={k: v["tile_cols"] for k, v in tuning.items()})
+                tuning={k: v["tile_cols"] for k, v in tuning.items()},
+                variants={k: v["variant"] for k, v in tuning.items()})
 
 
 def fft_bench(torch, n, reps=3):
@@ -448,7 +450,7 @@ def main():
         log("mixed %.1f Mpts*stages/s, %.1f ms/step" % (rm["value"], rm["ms_per_step"]))
         mixed = dict(value=round(rm["value"], 2), ms_per_step=round(rm["ms_per_step"], 3),
                      dtype="f32 FFT/pointwise/elastic, f64 stage sums and error", kernels=rm["kernels"],
-                     tuning=rm["tuning"],
+                     tuning=rm["tuning"], variants=rm["variants"],
                      speedup_vs_fp64=round(rm["value"] / r64["value"], 3))
     del ct, et
     torch.cuda.empty_cache()
@@ -487,7 +489,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "%d^3 ARK4(3)6L fixed dt=%g, %d seeded nuclei (radius 2-5, spacing 8), "
                                "6 stages per step" % (n, args.dt, spec["n_nuclei"]),
-                   "grid": n, "stages_per_step": 6, "dt": args.dt, "tile_cols": r64["tuning"]},
+                   "grid": n, "stages_per_step": 6, "dt": args.dt, "tile_cols": r64["tuning"],
+                   "tile_variants": r64["variants"]},
         "roofline": roofline,
         "kernels": kt,
         "mixed": mixed,

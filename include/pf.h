@@ -192,11 +192,15 @@ pf_status pf_profile_get(pf_ctx* ctx, int32_t cls, double* total_ms, int64_t* la
 
 /* Autotuner for the FFT tile plans.  Every column (y/z) pass kind
  * ("colfft", "stage_invz", "zpass_elastic", "zpass_fwd_ac") has two tile
- * variants (kx columns per work-group; see pf_tuning_get).  pf_autotune
- * times each variant `reps` times on this context's own buffers and keeps the
- * faster one; it overwrites the stage derivative arrays (call it between
- * steps, never inside one) and leaves the state untouched.  pf_tuning_set
- * forces a variant (0 or 1).  Kinds are 0 .. pf_tuning_kinds()-1;
+ * variants (kx columns per work-group; see pf_tuning_get); "colfft" has a
+ * third for lines of 128 or more: the variant-1 tile in a persistent
+ * work-group whose loader wavefronts fetch the next tile while the others
+ * transform the current one.  pf_autotune times each variant `reps` times on
+ * this context's own buffers and keeps the fastest; it overwrites the stage
+ * derivative arrays (call it between steps, never inside one) and leaves the
+ * state untouched.  pf_tuning_set forces a variant (PF_ERR_ARG for one that
+ * does not exist for this grid); pf_tuning_ms returns the last timing of a
+ * variant (0 if never timed).  Kinds are 0 .. pf_tuning_kinds()-1;
  * pf_tuning_name never returns NULL ("" for an invalid kind). */
 pf_status pf_autotune(pf_ctx* ctx, int32_t reps);
 int32_t pf_tuning_kinds(void);
@@ -204,6 +208,7 @@ const char* pf_tuning_name(int32_t kind);
 pf_status pf_tuning_get(pf_ctx* ctx, int32_t kind, int32_t* variant, int32_t* tile_cols,
                         int32_t* end_radix, double* ms_v0, double* ms_v1);
 pf_status pf_tuning_set(pf_ctx* ctx, int32_t kind, int32_t variant);
+pf_status pf_tuning_ms(pf_ctx* ctx, int32_t kind, int32_t variant, double* ms);
 
 /* ---- Batched ensembles (many independent simulations of uneven sizes) ----
  * n members, each with its own pf_params (cubic grids of 32, 48, 64, 96 or

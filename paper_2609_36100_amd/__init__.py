@@ -174,7 +174,7 @@ class Solver:
 
     # -- tile plans -------------------------------------------------------------
     def autotune(self, reps=3):
-        """Time both tile variants of every column pass and keep the faster ones."""
+        """Time the tile variants of every column pass and keep the fastest."""
         _lib.check(_lib.lib().pf_autotune(self._h, int(reps)), "pf_autotune")
         return self.tuning()
 
@@ -186,8 +186,10 @@ class Solver:
             m0, m1 = ctypes.c_double(), ctypes.c_double()
             _lib.check(L.pf_tuning_get(self._h, k, ctypes.byref(v), ctypes.byref(tx), ctypes.byref(re_),
                                        ctypes.byref(m0), ctypes.byref(m1)), "pf_tuning_get")
+            m2 = ctypes.c_double()
+            _lib.check(L.pf_tuning_ms(self._h, k, 2, ctypes.byref(m2)), "pf_tuning_ms")
             out[L.pf_tuning_name(k).decode()] = dict(variant=v.value, tile_cols=tx.value,
-                                                     end_radix=re_.value, ms=[m0.value, m1.value])
+                                                     end_radix=re_.value, ms=[m0.value, m1.value, m2.value])
         return out
 
     def set_tuning(self, kind, variant):

@@ -107,6 +107,7 @@ _SIGS = {
                                      ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                                      ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
     "pf_tuning_set": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32]),
+    "pf_tuning_ms": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]),
     "pf_ensemble_init": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(Params), ctypes.c_void_p,
                                         ctypes.POINTER(ctypes.c_void_p)]),
     "pf_ensemble_finalize": (None, [ctypes.c_void_p]),

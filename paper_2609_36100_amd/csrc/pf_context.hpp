@@ -132,7 +132,8 @@ struct pf_ctx {
 
   // column-kernel tile variants (see col_tx) and the autotuner's timings
   int var[pf::CK_COUNT] = {1, 1, 1, 1};
-  double tune_ms[pf::CK_COUNT][2] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
+  double tune_ms[pf::CK_COUNT][3] = {};
+  int num_cu = 256;  // compute units of the device (persistent launches)
 
   // per-kernel-class HIP-event timing (off by default)
   bool prof_on = false;

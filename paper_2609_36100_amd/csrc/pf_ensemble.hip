@@ -266,15 +266,21 @@ __global__ void __launch_bounds__(256) kb_finalize(const EMemb<T, TE>* mem, cons
     const int x = (int)(i % g.nxh);
     const long long idx = (i / g.nxh) * g.P + x;
     const cx<double> y0 = y[idx];
+    // all the stage loads of one element are issued before any is used
+    cx<double> fi[6], fe[6];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+      const bool hasI = j < fc.s && (fc.bI[j] != 0.0 || (fc.want_err && fc.dI[j] != 0.0));
+      const bool hasE = j < fc.s && (fc.bE[j] != 0.0 || (fc.want_err && fc.dE[j] != 0.0));
+      fi[j] = hasI ? e.FI[j][idx] : mk(0.0, 0.0);
+      fe[j] = hasE ? to_d(e.FE[j][idx]) : mk(0.0, 0.0);
+    }
     cx<double> inc = mk(0.0, 0.0), err = mk(0.0, 0.0);
-    for (int j = 0; j < fc.s; ++j) {
-      const bool hasI = fc.bI[j] != 0.0 || (fc.want_err && fc.dI[j] != 0.0);
-      const bool hasE = fc.bE[j] != 0.0 || (fc.want_err && fc.dE[j] != 0.0);
-      const cx<double> fi = hasI ? e.FI[j][idx] : mk(0.0, 0.0);
-      const cx<double> fe = hasE ? to_d(e.FE[j][idx]) : mk(0.0, 0.0);
-      if (fc.bI[j] != 0.0) inc = inc + (dt * fc.bI[j]) * fi;
-      if (fc.bE[j] != 0.0) inc = inc + (dt * fc.bE[j]) * fe;
-      if (fc.want_err) err = err + ((dt * fc.dI[j]) * fi + (dt * fc.dE[j]) * fe);
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+      if (j >= fc.s) break;
+      inc = inc + ((dt * fc.bI[j]) * fi[j] + (dt * fc.bE[j]) * fe[j]);
+      err = err + ((dt * fc.dI[j]) * fi[j] + (dt * fc.dE[j]) * fe[j]);
     }
     const cx<double> yn = y0 + inc;
     ynew[idx] = yn;

@@ -137,7 +137,21 @@ __host__ __device__ constexpr int plan_prod(int n, int q, int re) {
   return p;
 }
 
-template <typename T, int N, int S, int Q, int RE>
+// Work-group barrier for LDS exchanges only: waits for this wavefront's LDS
+// accesses, not for its outstanding global memory operations (a plain
+// __syncthreads also drains in-flight global loads and stores, including
+// loads that land in LDS).  The memory clobber keeps the compiler from moving
+// memory accesses across it.
+__device__ inline void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+template <bool LB>
+__device__ inline void xbar() {
+  if constexpr (LB)
+    lds_barrier();
+  else
+    __syncthreads();
+}
+
+template <typename T, int N, int S, int Q, int RE, bool LB = false>
 struct MidPass {
   template <class Buf>
   __device__ static inline void run(int tid, const cx<T>* tw, Buf buf, bool act) {
@@ -161,7 +175,7 @@ struct MidPass {
           dft<r, S>(v[j]);
         }
       }
-      __syncthreads();
+      xbar<LB>();
 #pragma unroll
       for (int j = 0; j < PER; ++j) {
         const int b = tid + j * TL;
@@ -171,8 +185,8 @@ struct MidPass {
           for (int t = 0; t < r; ++t) buf((b - k) * r + k + t * p) = v[j][t];
         }
       }
-      __syncthreads();
-      MidPass<T, N, S, Q + 1, RE>::run(tid, tw, buf, act);
+      xbar<LB>();
+      MidPass<T, N, S, Q + 1, RE, LB>::run(tid, tw, buf, act);
     }
   }
 };
@@ -184,7 +198,7 @@ struct MidPass {
 // the LDS region behind `buf` must hold N values.  Threads with act = false
 // only take part in the barriers (work-groups shared by lines of different
 // lengths have idle threads).
-template <typename T, int N, int S, int RE = 8, class Buf>
+template <typename T, int N, int S, int RE = 8, bool LB = false, class Buf>
 __device__ inline void line_fft(cx<T>* a, int tid, const cx<T>* tw, Buf buf, bool act = true) {
   constexpr Plan PL = plan(N, RE);
   static_assert(PL.ok, "unsupported line length");
@@ -192,13 +206,13 @@ __device__ inline void line_fft(cx<T>* a, int tid, const cx<T>* tw, Buf buf, boo
   constexpr int TL = N / R0;
   dft<R0, S>(a);
   if constexpr (PL.np > 1) {
-    __syncthreads();
+    xbar<LB>();
     if (act) {
 #pragma unroll
       for (int t = 0; t < R0; ++t) buf(tid * R0 + t) = a[t];
     }
-    __syncthreads();
-    MidPass<T, N, S, 1, RE>::run(tid, tw, buf, act);
+    xbar<LB>();
+    MidPass<T, N, S, 1, RE, LB>::run(tid, tw, buf, act);
     if (act) {
 #pragma unroll
       for (int t = 0; t < R0; ++t) a[t] = buf(tid + t * TL);
@@ -389,6 +403,114 @@ __global__ void __launch_bounds__((ColGeo<N, TX, RE>::THREADS))
 k_colfft(const cx<T>* in, cx<T>* out, Geo g, int nf, const cx<T>* tw, T scale) {
   __shared__ cx<T> lds[N * ColGeo<N, TX, RE>::LD];
   body_colfft<T, N, TX, RE, S, AXIS>(in, out, g, nf, tw, scale, xcd_tile(blockIdx.x, gridDim.x), threadIdx.x, lds);
+}
+
+// ---- wave-specialised column FFT (persistent) ------------------------------
+// The plain column pass alternates a load phase and an FFT phase per
+// work-group, so HBM idles while the butterflies run.  Here each work-group
+// has CG::THREADS compute threads and WS_LOADERS loader threads and walks the
+// items (field, tile) blockIdx.x, blockIdx.x + gridDim.x, ...: while the
+// compute threads transform item i (exchanges in `xch`), the loader threads
+// have item i + 1 copied from HBM straight into the landing buffer `land`
+// (global_load_lds_dwordx4: 16 bytes per lane, lane l of a wavefront writing
+// bytes [16 l, 16 l + 16) after the wavefront's LDS base), holding no
+// registers meanwhile; the compute threads pick it up after the next barrier.
+// Loader threads take part in every barrier of line_fft with act = false.
+// The exchanges synchronise with LDS-only barriers so that neither the
+// loaders' copies nor the compute threads' stores are drained at them, and
+// the twiddles are read from LDS.  Columns past the last valid kx are loaded from a clamped in-row address and
+// never stored (every column is transformed on its own).
+constexpr int WS_LOADERS = 256;
+template <typename T, int N, int TX, int RE = 8>
+constexpr bool ws_ok() {
+  constexpr int V = 16 / (int)sizeof(cx<T>);  // values per 16-byte copy
+  return N >= 128 && TX % V == 0 && (N * TX) % (WS_LOADERS * V) == 0 &&
+         TX * line_threads(N, RE) + WS_LOADERS <= 1024;
+}
+
+template <typename T>
+__device__ inline void lds_dma16(const void* src, void* lds_wave_base) {
+  __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)lds_wave_base, 16, 0, 0);
+}
+
+template <typename T, int N, int TX, int RE, int S, int AXIS>
+__global__ void __launch_bounds__((ColGeo<N, TX, RE>::THREADS + WS_LOADERS))
+k_colfft_ws(const cx<T>* in, cx<T>* out, Geo g, int nf, const cx<T>* tw, T scale) {
+  using CG = ColGeo<N, TX, RE>;
+  static_assert(ws_ok<T, N, TX, RE>(), "loader tiling");
+  constexpr int CT = CG::THREADS;
+  constexpr int V = 16 / (int)sizeof(cx<T>);        // values per lane and load
+  constexpr int PER_SWEEP = WS_LOADERS * V;          // values one sweep of all loaders moves
+  constexpr int NE = N * TX / PER_SWEEP;             // sweeps per item
+  static_assert(N * TX % PER_SWEEP == 0, "loader sweeps");
+  __shared__ __attribute__((aligned(16))) cx<T> xch[N * CG::LD];
+  __shared__ __attribute__((aligned(16))) cx<T> land[N * TX];
+  __shared__ __attribute__((aligned(16))) cx<T> twl[N];  // twiddles: no global loads inside the loop
+  const int tid = threadIdx.x;
+  for (int j = tid; j < N; j += CT + WS_LOADERS) twl[j] = tw[j];
+  const bool comp = tid < CT;
+  const int lt = tid - CT;  // loader index
+  const int col = tid % TX;
+  const int bf = comp ? tid / TX : 0;
+  const int nbx = (g.nxh + TX - 1) / TX;
+  const long long ntile = (long long)nbx * (AXIS == 1 ? g.nz : g.ny);
+  const long long nitems = ntile * nf;
+  const long long lstride = AXIS == 1 ? (long long)g.P : (long long)g.ny * g.P;
+  // start of item it's tile (column xb * TX) and the tile's first kx
+  auto tile_base = [&](long long it, int& x0) -> long long {
+    const int f = (int)(it / ntile);
+    const long long tile = it % ntile;
+    const int xb = (int)(tile % nbx);
+    const long long o = tile / nbx;
+    x0 = xb * TX;
+    return f * g.fs + (AXIS == 1 ? o * g.ny * g.P : o * g.P);
+  };
+  // loader: copy item it into land
+  auto load_item = [&](long long it) {
+    int x0;
+    const long long tb = tile_base(it, x0);
+#pragma unroll
+    for (int e = 0; e < NE; ++e) {
+      const int flat = e * PER_SWEEP + lt * V;  // first of this lane's V values in land
+      const int q = flat / TX, c0 = flat % TX;
+      int x = x0 + c0;
+      if (x > g.P - V) x = g.P - V;
+      const int wave_first = e * PER_SWEEP + (lt & ~63) * V;
+      lds_dma16<T>(in + tb + q * lstride + x, land + wave_first);
+    }
+  };
+  auto xbuf = [&](int pos) -> cx<T>& { return xch[pos * CG::LD + col]; };
+  long long it = blockIdx.x;
+  if (!comp && it < nitems) {
+    load_item(it);
+    __builtin_amdgcn_s_waitcnt(0);
+  }
+  __syncthreads();
+  for (; it < nitems; it += gridDim.x) {
+    const long long nxt = it + gridDim.x;
+    cx<T> a[CG::R0];
+    if (comp) {
+#pragma unroll
+      for (int t = 0; t < CG::R0; ++t) a[t] = land[(bf + t * CG::TL) * TX + col];
+    } else {
+#pragma unroll
+      for (int t = 0; t < CG::R0; ++t) a[t] = mk<T>(0, 0);
+    }
+    lds_barrier();  // the landing buffer has been read
+    if (!comp && nxt < nitems) load_item(nxt);
+    line_fft<T, N, S, RE, true>(a, bf, twl, xbuf, comp);
+    if (comp) {
+      int x0;
+      const long long tb = tile_base(it, x0);
+      if (x0 + col < g.nxh) {
+#pragma unroll
+        for (int t = 0; t < CG::R0; ++t) out[tb + x0 + col + (bf + t * CG::TL) * lstride] = scale * a[t];
+      }
+    } else {
+      __builtin_amdgcn_s_waitcnt(0);
+    }
+    lds_barrier();  // the next item has landed (the loaders waited for their copies)
+  }
 }
 
 // ---- K-E: forward z-FFT of theta, elastic solve, explicit CH, inverse z ----
@@ -769,16 +891,22 @@ __global__ void __launch_bounds__(256) k_finalize(FinArgs<TE> fa, Geo g) {
     const long long fr = i / g.nxh;  // f * nrow + row
     const long long idx = fr * g.P + x;
     const cx<double> y0 = fa.y[idx];
+    // every stage array this step reads is loaded before any is used, so the
+    // loads of one element are in flight together (unused weights are zero)
+    cx<double> fi[6], fe[6];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+      const bool hasI = j < fa.s && (fa.bI[j] != 0.0 || (fa.want_err && fa.dI[j] != 0.0));
+      const bool hasE = j < fa.s && (fa.bE[j] != 0.0 || (fa.want_err && fa.dE[j] != 0.0));
+      fi[j] = hasI ? fa.FI[j][idx] : mk(0.0, 0.0);
+      fe[j] = hasE ? to_d(fa.FE[j][idx]) : mk(0.0, 0.0);
+    }
     cx<double> inc = mk(0.0, 0.0), err = mk(0.0, 0.0);
-    for (int j = 0; j < fa.s; ++j) {
-      const bool hasI = fa.bI[j] != 0.0 || (fa.want_err && fa.dI[j] != 0.0);
-      const bool hasE = fa.bE[j] != 0.0 || (fa.want_err && fa.dE[j] != 0.0);
-      cx<double> fi = mk(0.0, 0.0), fe = mk(0.0, 0.0);
-      if (hasI) fi = fa.FI[j][idx];
-      if (hasE) fe = to_d(fa.FE[j][idx]);
-      if (fa.bI[j] != 0.0) inc = inc + fa.bI[j] * fi;
-      if (fa.bE[j] != 0.0) inc = inc + fa.bE[j] * fe;
-      if (fa.want_err) err = err + (fa.dI[j] * fi + fa.dE[j] * fe);
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+      if (j >= fa.s) break;
+      inc = inc + (fa.bI[j] * fi[j] + fa.bE[j] * fe[j]);
+      err = err + (fa.dI[j] * fi[j] + fa.dE[j] * fe[j]);
     }
     const cx<double> yn = y0 + inc;
     fa.ynew[idx] = yn;

@@ -79,6 +79,17 @@ constexpr int col_tx(int n, int kind, int elem_bytes, int v) {
   while (tx * line_threads(n, col_re(kind)) < 64 && tx < 16) tx *= 2;
   return tx;
 }
+// Whether the wave-specialised column FFT (variant 2 of "colfft") exists for
+// lines of length n with elements of elem_bytes.
+static bool ws_supported(int n, int elem_bytes) {
+  bool ok = false;
+  col_dispatch(n, [&](auto NC) {
+    constexpr int N = decltype(NC)::value;
+    ok = elem_bytes == 16 ? ws_ok<double, N, col_tx(N, CK_FFT, 16, 1)>()
+                          : ws_ok<float, N, col_tx(N, CK_FFT, 8, 1)>();
+  });
+  return ok;
+}
 template <class F>
 static void with_variant(int v, F&& f) {
   if (v)
@@ -225,10 +236,22 @@ static bool launch_colfft(pf_ctx* c, const cx<T>* in, cx<T>* out, int nf, T scal
   const int other = AXIS == 1 ? g.nz : g.ny;
   return col_dispatch(n, [&](auto NC) {
     constexpr int N = decltype(NC)::value;
-    with_variant(c->var[CK_FFT], [&](auto VC) {
+    const int var = c->var[CK_FFT];
+    with_variant(var ? 1 : 0, [&](auto VC) {
       constexpr int RE = col_re(CK_FFT);
       constexpr int TX = col_tx(N, CK_FFT, sizeof(cx<T>), decltype(VC)::value);
       const int nbx = (g.nxh + TX - 1) / TX;
+      if constexpr (ws_ok<T, N, TX, RE>()) {
+        if (var == 2) {
+          // persistent wave-specialised pass: one work-group per compute unit
+          const long long items = (long long)nbx * other * nf;
+          const int grid = (int)std::min<long long>(items, c->num_cu);
+          k_colfft_ws<T, N, TX, RE, S, AXIS>
+              <<<dim3(grid), dim3(ColGeo<N, TX, RE>::THREADS + WS_LOADERS), 0, c->stream>>>(
+                  in, out, g, nf, tw<T>(c, AXIS == 1 ? 1 : 0), scale);
+          return;
+        }
+      }
       k_colfft<T, N, TX, RE, S, AXIS><<<dim3(nbx * other), dim3(ColGeo<N, TX, RE>::THREADS), 0, c->stream>>>(
           in, out, g, nf, tw<T>(c, AXIS == 1 ? 1 : 0), scale);
     });
@@ -478,6 +501,9 @@ void ctx_setup(pf_ctx* c, const pf_params* p, hipStream_t stream) {
   if (c->p.max_rejects <= 0) c->p.max_rejects = 10;
   c->stream = stream;
   hipGetDevice(&c->device);
+  int ncu = 0;
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device) == hipSuccess && ncu > 0)
+    c->num_cu = ncu;
   c->mixed = p->precision == PF_MIXED;
   Geo& g = c->g;
   g.nx = p->nx;
@@ -928,7 +954,9 @@ static pf_status autotune_impl(pf_ctx* c, int reps) {
   for (int k = 0; k < CK_COUNT; ++k) {
     double best = 1e300;
     int best_v = 0;
-    for (int v = 0; v < 2; ++v) {
+    const int nvar = (k == CK_FFT && ws_supported(c->g.ny, sizeof(cx<T>)) && ws_supported(c->g.nz, sizeof(cx<T>)))
+                         ? 3 : 2;
+    for (int v = 0; v < nvar; ++v) {
       c->var[k] = v;
       auto run = [&]() {
         switch (k) {
@@ -974,7 +1002,7 @@ pf_status pf_tuning_get(pf_ctx* c, int32_t kind, int32_t* variant, int32_t* tile
   const int v = c->var[kind];
   const int eb = c->mixed ? (int)sizeof(cx<float>) : (int)sizeof(cx<double>);
   if (variant) *variant = v;
-  if (tile_cols) *tile_cols = col_tx(c->g.nz, kind, eb, v);
+  if (tile_cols) *tile_cols = col_tx(c->g.nz, kind, eb, v ? 1 : 0);
   if (end_radix) *end_radix = col_re(kind);
   if (ms_v0) *ms_v0 = c->tune_ms[kind][0];
   if (ms_v1) *ms_v1 = c->tune_ms[kind][1];
@@ -982,8 +1010,17 @@ pf_status pf_tuning_get(pf_ctx* c, int32_t kind, int32_t* variant, int32_t* tile
 }
 
 pf_status pf_tuning_set(pf_ctx* c, int32_t kind, int32_t variant) {
-  if (!c || kind < 0 || kind >= CK_COUNT || variant < 0 || variant > 1) return PF_ERR_ARG;
+  if (!c || kind < 0 || kind >= CK_COUNT || variant < 0 || variant > 2) return PF_ERR_ARG;
+  if (variant == 2 && !(kind == CK_FFT && ws_supported(c->g.ny, c->mixed ? 8 : 16) &&
+                        ws_supported(c->g.nz, c->mixed ? 8 : 16)))
+    return PF_ERR_ARG;
   c->var[kind] = variant;
+  return PF_OK;
+}
+
+pf_status pf_tuning_ms(pf_ctx* c, int32_t kind, int32_t variant, double* ms) {
+  if (!c || kind < 0 || kind >= CK_COUNT || variant < 0 || variant > 2 || !ms) return PF_ERR_ARG;
+  *ms = c->tune_ms[kind][variant];
   return PF_OK;
 }
 

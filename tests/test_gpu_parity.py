@@ -239,23 +239,52 @@ def test_mixed_precision_rhs_error_bound(torch, params, n):
         assert errs[f] < 1e-4
 
 
-@pytest.mark.parametrize("shape", [(64, 64, 64), (96, 96, 96), (128, 64, 96)])
-@pytest.mark.parametrize("variant", [0, 1])
+@pytest.mark.parametrize("shape", [(64, 64, 64), (96, 96, 96), (128, 64, 96), (128, 128, 128), (160, 128, 96)])
+@pytest.mark.parametrize("variant", [0, 1, 2])
 def test_tile_variants_match_oracle(torch, params, shape, variant):
-    """Every column-pass tile variant the autotuner may pick gives the oracle's RHS."""
+    """Every column-pass tile variant the autotuner may pick gives the oracle's RHS
+    (variant 2, the persistent column FFT with loader wavefronts, exists for
+    y and z lines of 128 or more)."""
     _say("tile variant", variant, shape)
     c, eta = _rand_fields(shape, seed=3)
     m = om.Model(shape, params)
     y = om.to_kspace(c, eta)
     FI, FE = m.rhs(y)
     with _solver(shape, params) as s:
-        for k in range(4):
-            s.set_tuning(k, variant)
+        if variant == 2:
+            from paper_2609_36100_amd import PFError
+            if min(shape[0], shape[1]) < 128:   # (nz, ny, nx): the z and y line lengths
+                with pytest.raises(PFError):
+                    s.set_tuning(0, 2)
+                return
+            s.set_tuning(0, 2)
+            for k in range(1, 4):
+                s.set_tuning(k, 1)
+        else:
+            for k in range(4):
+                s.set_tuning(k, variant)
         fI, fE = s.rhs(s.kspace_from_numpy(y))
         gI, gE = s.kspace_to_numpy(fI), s.kspace_to_numpy(fE)
     for f in range(4):
         assert _rel(gI[f], FI[f]) < TOL
         assert _rel(gE[f], FE[f]) < TOL, (f, _rel(gE[f], FE[f]))
+
+
+def test_mixed_persistent_column_fft_matches_plain_variant(torch, params):
+    """FP32 column passes: the persistent variant computes what the plain one does."""
+    _say("mixed variant 2 vs 1, 128^3")
+    shape = (128, 128, 128)
+    c, eta = _rand_fields(shape, seed=5)
+    y = om.to_kspace(c, eta)
+    out = []
+    for v in (1, 2):
+        with _solver(shape, params, precision="mixed") as s:
+            s.set_tuning(0, v)
+            fI, fE = s.rhs(s.kspace_from_numpy(y))
+            out.append((s.kspace_to_numpy(fI), s.kspace_to_numpy(fE)))
+    for f in range(4):
+        assert _rel(out[1][0][f], out[0][0][f]) < 1e-12
+        assert _rel(out[1][1][f], out[0][1][f]) < 1e-6, f
 
 
 def test_autotune_then_step_matches_oracle(torch, params):
