@@ -7,9 +7,12 @@ the WRMS norm (Eq. wrms_norm) with weights (Eq. wrms_weights), and the
 accept-if-norm-at-most-one rule.  Only the stiff linear terms are implicit,
 so each implicit stage solve is a division by ``1 - dt A^I_ii L(k)`` per mode.
 
-Tables: first-order IMEX Euler (2-stage ARK form) and ARK4(3)6L[2]SA of
-Kennedy & Carpenter (2003, Appl. Numer. Math. 44), the fourth-order method
-the paper cites; coefficients are the published rationals.
+Tables: first-order IMEX Euler (2-stage ARK form); the second-order
+three-stage ARK2 of Giraldo, Kelly & Constantinescu (2013, SIAM J. Sci.
+Comput. 35), whose entries lie in Q(sqrt 2) and are kept exactly as
+a + b sqrt 2; ARK3(2)4L[2]SA and ARK4(3)6L[2]SA of Kennedy & Carpenter (2003,
+Appl. Numer. Math. 44), the third- and fourth-order methods the paper's
+order study cites; their coefficients are the published rationals.
 
 Readings (listed in the design doc): the WRMS vector is the reciprocal-space state
 scaled to unit norm (Parseval), modes weighted by their half-spectrum
@@ -58,6 +61,62 @@ def _q(s):
     return Fr(s)
 
 
+class QS2:
+    """Exact element a + b sqrt(2) of Q(sqrt 2), a and b rational."""
+
+    def __init__(self, a, b=0):
+        self.a, self.b = Fr(a), Fr(b)
+
+    @staticmethod
+    def _c(x):
+        return x if isinstance(x, QS2) else QS2(x)
+
+    def __add__(self, o):
+        o = QS2._c(o)
+        return QS2(self.a + o.a, self.b + o.b)
+
+    __radd__ = __add__
+
+    def __neg__(self):
+        return QS2(-self.a, -self.b)
+
+    def __sub__(self, o):
+        return self + (-QS2._c(o))
+
+    def __rsub__(self, o):
+        return QS2._c(o) - self
+
+    def __mul__(self, o):
+        o = QS2._c(o)
+        return QS2(self.a * o.a + 2 * self.b * o.b, self.a * o.b + self.b * o.a)
+
+    __rmul__ = __mul__
+
+    def __pow__(self, k):
+        out = QS2(1)
+        for _ in range(int(k)):
+            out = out * self
+        return out
+
+    def __eq__(self, o):
+        o = QS2._c(o)
+        return self.a == o.a and self.b == o.b
+
+    def __ne__(self, o):
+        return not self == o
+
+    def __hash__(self):
+        return hash((self.a, self.b))
+
+    def __float__(self):
+        # a + b sqrt 2 in long double-free form: the two rationals in binary64 (the
+        # product's rounding error is below 2^-52 of the magnitude)
+        return float(self.a) + float(self.b) * 2.0 ** 0.5
+
+    def __repr__(self):
+        return "QS2(%s, %s)" % (self.a, self.b)
+
+
 def imex_euler():
     """First-order IMEX Euler as a 2-stage ARK pair (explicit first stage, implicit second)."""
     z, o = Fr(0), Fr(1)
@@ -104,7 +163,47 @@ def ark436l2sa():
     return Table("ark436l2sa", AE=AE, AI=AI, b=b, bt=bt, c=c, order=4, emb_order=3)
 
 
-TABLES = {"imex_euler": imex_euler, "ark436l": ark436l2sa}
+def ark2():
+    """ARK2 of Giraldo, Kelly & Constantinescu (2013): 3 stages, second order,
+    ESDIRK implicit part with gamma = 1 - 1/sqrt 2, stiffly accurate, explicit
+    weight alpha = (3 + 2 sqrt 2)/6 in the last row, embedded first-order
+    weights ((4 - sqrt 2)/8, (4 - sqrt 2)/8, 1/(2 sqrt 2))."""
+    z = QS2(0)
+    g = QS2(1, Fr(-1, 2))            # 1 - sqrt(2)/2
+    d = QS2(0, Fr(1, 4))             # sqrt(2)/4 = 1/(2 sqrt 2)
+    al = QS2(Fr(1, 2), Fr(1, 3))     # (3 + 2 sqrt 2)/6
+    c = [z, 2 * g, QS2(1)]
+    AE = [[z, z, z], [2 * g, z, z], [1 - al, al, z]]
+    AI = [[z, z, z], [g, g, z], [d, d, g]]
+    b = [d, d, g]
+    bt = [QS2(Fr(1, 2), Fr(-1, 8)), QS2(Fr(1, 2), Fr(-1, 8)), QS2(0, Fr(1, 4))]
+    return Table("ark2", AE=AE, AI=AI, b=b, bt=bt, c=c, order=2, emb_order=1)
+
+
+def ark324l2sa():
+    """ARK3(2)4L[2]SA, Kennedy & Carpenter 2003: 4 stages, ESDIRK implicit part,
+    stiffly accurate, embedded second-order weights."""
+    q = _q
+    g = q("1767732205903/4055673282236")
+    z = q(0)
+    AE = [[z] * 4 for _ in range(4)]
+    AE[1][0] = q("1767732205903/2027836641118")
+    AE[2][0], AE[2][1] = q("5535828885825/10492691773637"), q("788022342437/10882634858940")
+    AE[3][0], AE[3][1], AE[3][2] = (q("6485989280629/16251701735622"), q("-4246266847089/9704473918619"),
+                                    q("10755448449292/10357097424841"))
+    b = [q("1471266399579/7840856788654"), q("-4482444167858/7529755066697"),
+         q("11266239266428/11593286722821"), q("1767732205903/4055673282236")]
+    bt = [q("2756255671327/12835298489170"), q("-10771552573575/22201958757719"),
+          q("9247589265047/10645013368117"), q("2193209047091/5459859503100")]
+    AI = [[z] * 4 for _ in range(4)]
+    AI[1][0], AI[1][1] = q("1767732205903/4055673282236"), g
+    AI[2][0], AI[2][1], AI[2][2] = q("2746238789719/10658868560708"), q("-640167445237/6845629431997"), g
+    AI[3] = list(b)
+    c = [z, q("1767732205903/2027836641118"), q("3/5"), q(1)]
+    return Table("ark324l2sa", AE=AE, AI=AI, b=b, bt=bt, c=c, order=3, emb_order=2)
+
+
+TABLES = {"imex_euler": imex_euler, "ark2": ark2, "ark324l": ark324l2sa, "ark436l": ark436l2sa}
 
 
 def ark_step(y, dt, table, f_explicit, Lsym):

@@ -84,6 +84,40 @@ def test_ark436_order_conditions_exact():
     assert max(abs(float(r)) for r in res4) > 1e-6
 
 
+def test_ark2_order_conditions_exact_in_q_sqrt2():
+    """ARK2's entries are exact in Q(sqrt 2): row sums, second order for both
+    halves and their coupling, first-order embedding, stiff accuracy."""
+    t = ark.ark2()
+    for A in (t.AE_q, t.AI_q):
+        for i in range(t.s):
+            assert sum(A[i]) == t.c_q[i]
+    res = _order_conditions([t.AE_q, t.AI_q], t.b_q, t.c_q, 2)
+    assert all(r == 0 for r in res)
+    assert _order_conditions([t.AE_q, t.AI_q], t.bt_q, t.c_q, 1) == [0]
+    assert _order_conditions([t.AE_q, t.AI_q], t.bt_q, t.c_q, 2)[1] != 0   # genuinely first order
+    assert any(r != 0 for r in _order_conditions([t.AE_q, t.AI_q], t.b_q, t.c_q, 3))
+    assert list(t.AI_q[-1]) == list(t.b_q)                                  # stiffly accurate
+    g = t.AI_q[1][1]
+    assert all(t.AI_q[i][i] == g for i in range(1, t.s)) and t.AI_q[0][0] == 0
+    assert g * g - 2 * g + ark.QS2(Fr(1, 2)) == 0    # gamma = 1 - 1/sqrt 2 solves g^2 - 2g + 1/2 = 0
+
+
+def test_ark324_order_conditions_exact():
+    t = ark.ark324l2sa()
+    for A in (t.AE_q, t.AI_q):
+        for i in range(t.s):
+            assert abs(float(sum(A[i]) - t.c_q[i])) < 1e-20
+    res = _order_conditions([t.AE_q, t.AI_q], t.b_q, t.c_q, 3)
+    assert len(res) == 5
+    assert max(abs(float(r)) for r in res) < 1e-25
+    res2 = _order_conditions([t.AE_q, t.AI_q], t.bt_q, t.c_q, 2)
+    assert max(abs(float(r)) for r in res2) < 1e-25
+    assert max(abs(float(r)) for r in _order_conditions([t.AE_q, t.AI_q], t.bt_q, t.c_q, 3)) > 1e-4
+    assert max(abs(float(r)) for r in _order_conditions([t.AE_q, t.AI_q], t.b_q, t.c_q, 4)) > 1e-4
+    assert list(t.AI_q[-1]) == list(t.b_q)
+    assert all(t.AI_q[i][i] == t.AI_q[1][1] for i in range(1, t.s))
+
+
 def test_imex_euler_order_conditions():
     t = ark.imex_euler()
     assert _order_conditions([t.AE_q], t.b_q, t.c_q, 1) == [0]
@@ -93,7 +127,7 @@ def test_imex_euler_order_conditions():
     assert _order_conditions([t.AI_q], t.bI_q, t.c_q, 2)[1] != 0
 
 
-@pytest.mark.parametrize("table", ["imex_euler", "ark436l"])
+@pytest.mark.parametrize("table", ["imex_euler", "ark2", "ark324l", "ark436l"])
 @pytest.mark.parametrize("lam", [(-3.0, -0.5), (-50.0, 0.2), (-0.1, -1.5), (0.4, -0.3)])
 def test_stability_function_on_scalar_problem(table, lam):
     t = ark.TABLES[table]()
@@ -186,7 +220,7 @@ def test_mass_conserved_bitwise_and_energy_decreases(params):
 
 @pytest.mark.parametrize("split", [1, 0])
 @pytest.mark.parametrize("W", [1.0, -1.0])
-@pytest.mark.parametrize("table", ["imex_euler", "ark436l"])
+@pytest.mark.parametrize("table", ["imex_euler", "ark2", "ark324l", "ark436l"])
 def test_linearised_cahn_hilliard_amplification(params, split, W, table):
     """eta = 0 is invariant and the c equation is exactly linear: per-mode amplification R."""
     p = dict(params)
@@ -230,6 +264,8 @@ def test_observed_order_linear_single_mode(params):
     sigma = -m.M * k2 * (2 * m.W + m.kappa_c * k2)
     T = 2.0
     for table, dts, lo, hi in (("imex_euler", [0.2, 0.1, 0.05, 0.025], 0.9, 1.1),
+                               ("ark2", [0.1, 0.05, 0.025, 0.0125], 1.8, 2.3),
+                               ("ark324l", [0.4, 0.2, 0.1, 0.05], 2.8, 3.4),
                                ("ark436l", [0.4, 0.2, 0.1, 0.05], 3.7, 4.6)):
         errs = []
         for dt in dts:
@@ -252,6 +288,8 @@ def test_observed_order_nonlinear_self_convergence(params):
         y, _, _ = ark.ark_step(y, 0.05, t, m.f_explicit, L)
     T = 2.0
     for table, dts, lo, hi in (("imex_euler", [0.05, 0.025, 0.0125, 0.00625], 0.9, 1.1),
+                               ("ark2", [0.2, 0.1, 0.05, 0.025], 1.8, 2.3),
+                               ("ark324l", [0.4, 0.2, 0.1, 0.05], 2.7, 3.4),
                                ("ark436l", [0.4, 0.2, 0.1, 0.05], 3.6, 4.4)):
         ref_int = ark.Integrator(m, table=table, dt0=dts[-1] / 16)
         yref, _ = ref_int.advance(y.copy(), 0.0, T)
