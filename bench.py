@@ -12,7 +12,10 @@ are resident on the GPU before timing starts.
 Prints ONE JSON line.  Extra objects:
   roofline      dominant kernel's algorithmic bytes per launch / average
                 launch time (HIP events around each launch on the library's
-                stream, inside the timed region) against 8 TB/s HBM;
+                stream, inside the timed region) against 8 TB/s HBM, and
+                against the streaming probe's copy rate below;
+  hbm_probe     what plain streaming kernels draw from HBM on this device
+                (copy, read-only, eleven reads + one write), GB/s;
   kernels       the same for every kernel class;
   mixed         the mixed-precision run of the same workload;
   fft           standalone forward + inverse 3D real FFT of 4 fields (FP64);
@@ -357,6 +360,64 @@ def fno_bench(torch, t_final, runs, val_runs, snapshots, epochs, train_s, member
     return out
 
 
+def orders_bench(torch, n, t_final):
+    """Work-precision of the four ImEx pairs on one seeded n^3 workload: state error
+    at t_final against a tight ARK4 reference, explicit RHS evaluations and wall
+    time (IMEX Euler with fixed steps, the embedded pairs adaptive over rtol)."""
+    import numpy as np
+    import pfinputs
+    from paper_2609_36100_amd import Solver, rel_l2
+    spec, c, eta = pfinputs.config("adaptive256", n=n)
+    out = dict(n=n, t_final=t_final, nuclei=spec["n_nuclei"], runs={})
+    log("orders: reference ARK4 rtol 1e-11")
+    with Solver(n, None, method="ark436l", adaptive=True, dt0=1e-3, rtol=1e-11, atol=1e-14) as s:
+        s.set_state(c, eta)
+        s.advance(t_final)
+        ref = s.get_state_device().clone()
+
+    def run(method, **kw):
+        with Solver(n, None, method=method, **kw) as s:
+            s.set_state(c, eta)
+            s.autotune(1) if n >= 128 else None
+            s.set_state(c, eta)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st = s.advance(t_final)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            u = s.get_state_device()
+        err = max(rel_l2(u[f], ref[f]) for f in range(4) if float(ref[f].abs().max()) > 0)
+        return dict(err=float("%.3e" % err), n_rhs=st["n_rhs"], steps=st["steps"], rejects=st["rejects"],
+                    wall_s=round(wall, 4))
+
+    for dt in (0.02, 0.01, 0.005, 0.0025):
+        out["runs"].setdefault("imex_euler", []).append(dict(dt=dt, **run("imex_euler", dt0=dt)))
+    for method in ("ark2", "ark324l", "ark436l"):
+        for rtol in (1e-4, 1e-5, 1e-6, 1e-7, 1e-8):
+            r = run(method, adaptive=True, dt0=1e-3, rtol=rtol, atol=rtol * 1e-3)
+            out["runs"].setdefault(method, []).append(dict(rtol=rtol, **r))
+            log("orders: %s rtol %g: err %.2e, %d RHS, %.3f s" % (method, rtol, r["err"], r["n_rhs"], r["wall_s"]))
+
+    # wall time each method needs for a given error, by log-log interpolation
+    def cost_at(method, target):
+        pts = sorted((r["err"], r["wall_s"]) for r in out["runs"][method] if r["err"] > 0)
+        for (e0, w0), (e1, w1) in zip(pts, pts[1:]):
+            if e0 <= target <= e1:
+                f = (np.log(target) - np.log(e0)) / (np.log(e1) - np.log(e0))
+                return float(np.exp(np.log(w0) + f * (np.log(w1) - np.log(w0))))
+        return None
+    gains = {}
+    for target in (1e-4, 1e-5, 1e-6):
+        w4 = cost_at("ark436l", target)
+        row = {}
+        for mth in ("imex_euler", "ark2", "ark324l"):
+            w = cost_at(mth, target)
+            row[mth] = round(w / w4, 3) if (w and w4) else None
+        gains["%g" % target] = row
+    out["ark4_speedup_at_error"] = gains
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -367,7 +428,7 @@ def main():
     ap.add_argument("--skip-mixed", action="store_true")
     ap.add_argument("--skip-fft", action="store_true")
     ap.add_argument("--skip-cpu", action="store_true")
-    ap.add_argument("--mode", choices=["throughput", "ensemble", "time_to_t", "fno"], default="throughput")
+    ap.add_argument("--mode", choices=["throughput", "ensemble", "time_to_t", "fno", "orders"], default="throughput")
     ap.add_argument("--runs", type=int, default=40, help="fno: training runs")
     ap.add_argument("--val-runs", type=int, default=4, help="fno: held-out runs")
     ap.add_argument("--snapshots", type=int, default=50, help="fno: snapshots per run")
@@ -424,6 +485,15 @@ def main():
                                                  "advance at rel-L2(c) 1e-3" % g["t_final"]},
                           "fno": r}), flush=True)
         return
+    if args.mode == "orders":
+        n = args.n if args.n != 512 else 128
+        r = orders_bench(torch, n, args.t_final or 2.0)
+        print(json.dumps({"metric": METRIC, "mode": "orders", "unit": "s", "value": None,
+                          "higher_is_better": False, "n_gpus": 1, "dtype": "f64", "data": "synthetic",
+                          "config": {"workload": "%d^3, %d seeded nuclei, to t=%g: IMEX Euler, ARK2, ARK3(2)4L, "
+                                                 "ARK4(3)6L work-precision" % (n, r["nuclei"], r["t_final"])},
+                          "orders": r}), flush=True)
+        return
     if args.mode == "time_to_t":
         n = args.n if args.n != 512 else 256
         r = time_to_t_bench(torch, n, args.t_final or 500.0, 1e-6, 1e-9)
@@ -434,6 +504,10 @@ def main():
                           "time_to_t": r}), flush=True)
         return
     n = args.n
+    from paper_2609_36100_amd import bandwidth_probe
+    probe = bandwidth_probe(1 << 30, 5)
+    log("streaming probe (GB/s): copy %.0f, read %.0f, 11 reads + 1 write %.0f"
+        % (probe["copy"], probe["read"], probe["multi"]))
     log("generating %d^3 seeded initial condition" % n)
     spec, c, eta = pfinputs.config("mixed512", n=n)
     ct = torch.from_numpy(c).cuda()
@@ -469,7 +543,9 @@ def main():
                     frac=d["frac"], traffic=traffic,
                     traffic_note="HBM bytes per launch from rocprofv3 FETCH_SIZE x2 + WRITE_SIZE x1 "
                                  "(copy-kernel calibration); algorithmic bytes per launch %.0f"
-                                 % d["bytes_per_launch"])
+                                 % d["bytes_per_launch"],
+                    probe_gbs=round(probe["copy"], 1),
+                    frac_of_probe=round(d["gbs"] / probe["copy"], 4))
     cpu = None
     if not args.skip_cpu:
         log("CPU oracle sample")
@@ -496,6 +572,7 @@ def main():
         "mixed": mixed,
         "fft": fft,
         "cpu_baseline": cpu,
+        "hbm_probe": {k: round(v, 1) for k, v in probe.items()},
     }
     print(json.dumps(line), flush=True)
 

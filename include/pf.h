@@ -52,7 +52,13 @@ typedef enum {
 
 typedef enum { PF_FP64 = 0, PF_MIXED = 1 } pf_precision;
 
-typedef enum { PF_IMEX_EULER = 1, PF_ARK436L = 4 } pf_method;
+/* ImEx-ARK pairs (Methods, "Time integration"; the orders of the paper's
+ * order study, Results, "Improved performance via time integration
+ * approach"): IMEX Euler as a 2-stage pair (1 explicit RHS per step, no
+ * embedding); ARK2 of Giraldo, Kelly & Constantinescu 2013 (3, first-order
+ * embedding); ARK3(2)4L[2]SA (4) and ARK4(3)6L[2]SA (6) of Kennedy &
+ * Carpenter 2003.  Adaptive stepping needs an embedded pair. */
+typedef enum { PF_IMEX_EULER = 1, PF_ARK2 = 2, PF_ARK324L = 3, PF_ARK436L = 4 } pf_method;
 
 /* Model, discretisation and integrator parameters.
  * Model (Methods, "Phase-field model formulation", dimensionless stand-in):
@@ -78,7 +84,7 @@ typedef struct {
   int32_t implicit_bulk_c;  /* 1: 2W k^2 implicit (default), 0: explicit */
   int32_t precision;        /* pf_precision */
   int32_t method;           /* pf_method */
-  int32_t adaptive;         /* 1: embedded-error step control (ARK436L only) */
+  int32_t adaptive;         /* 1: embedded-error step control (ARK2, ARK324L, ARK436L) */
   double dt0, rtol, atol, dt_min, dt_max;
   int32_t max_rejects;      /* consecutive rejections before PF_ERR_STEP_FAIL */
 } pf_params;
@@ -212,8 +218,8 @@ pf_status pf_tuning_ms(pf_ctx* ctx, int32_t kind, int32_t variant, double* ms);
 
 /* ---- Batched ensembles (many independent simulations of uneven sizes) ----
  * n members, each with its own pf_params (cubic grids of 32, 48, 64, 96 or
- * 128 points; method PF_ARK436L; one precision and one adaptivity setting for
- * all).  Every pass of the stage cycle is one launch covering all members;
+ * 128 points; one embedded method (PF_ARK2, PF_ARK324L or PF_ARK436L), one
+ * precision and one adaptivity setting for all).  Every pass of the stage cycle is one launch covering all members;
  * accept / reject and the next step size are decided on the device per
  * member; one attempted step of all members is captured once as a hipGraph
  * and replayed.  stream: a hipStream_t or NULL (then the ensemble creates its
@@ -322,6 +328,15 @@ pf_status pf_fno_advance(pf_fno* f, pf_ctx* plain, double* state, int32_t n_adv,
 /* ||a - b||_2 / ||b||_2 over n device float64 values (||a - b|| if b == 0),
  * ordered on hip_stream (NULL = default); synchronises that stream. */
 pf_status pf_rel_l2(const double* a, const double* b, int64_t n, void* hip_stream, double* out);
+
+/* Streaming-bandwidth probe (a measurement aid, not part of the method): on
+ * hip_stream (NULL = default) times a device copy of `bytes`, a read-only sum
+ * over `bytes`, and a kernel reading eleven arrays of `bytes` and writing one
+ * (the shape of the ARK4 update), best of `reps`; returns algorithmic GB/s of
+ * each.  Allocates and frees 12 x bytes of device memory; synchronises the
+ * stream.  PF_ERR_ARG for bytes < 1 MiB or reps < 1. */
+pf_status pf_bandwidth_probe(int64_t bytes, int32_t reps, void* hip_stream, double* copy_gbs, double* read_gbs,
+                             double* multi_gbs);
 
 /* Human-readable status name; never NULL. */
 const char* pf_status_string(pf_status s);

@@ -14,7 +14,7 @@ import numpy as np
 from . import _lib
 from ._lib import FnoStats, PFError, Stats, make_params  # noqa: F401
 
-__all__ = ["Solver", "Ensemble", "FNO", "FnoStats", "PFError", "make_params", "rel_l2", "size_supported"]
+__all__ = ["Solver", "Ensemble", "FNO", "FnoStats", "PFError", "make_params", "bandwidth_probe", "rel_l2", "size_supported"]
 
 
 def _torch():
@@ -35,7 +35,7 @@ class Solver:
 
     Parameters mirror ``pf_params``: ``n`` (int or (nx, ny, nz)), ``model``
     (dict of model constants, see ``pfinputs.default_params``), ``method``
-    ("imex_euler" | "ark436l"), ``precision`` ("fp64" | "mixed"), ``adaptive``,
+    ("imex_euler" | "ark2" | "ark324l" | "ark436l"), ``precision`` ("fp64" | "mixed"), ``adaptive``,
     ``dt0``, ``rtol``, ``atol``.
     """
 
@@ -222,7 +222,8 @@ class Ensemble:
 
     ``members`` is a list of dicts with keys ``n`` (32, 48, 64, 96 or 128) and
     optionally ``model`` plus any :func:`make_params` keyword (``adaptive``,
-    ``dt0``, ``rtol``, ``atol``, ``precision``; the method is ARK4(3)6L).
+    ``dt0``, ``rtol``, ``atol``, ``precision``, ``method`` among the embedded pairs,
+    ARK4(3)6L by default; one method for all members).
     """
 
     def __init__(self, members, stream=None):
@@ -322,6 +323,14 @@ class Ensemble:
     def set_tuning(self, kind, block_threads):
         _lib.check(_lib.lib().pf_ensemble_tuning_set(self._h, int(kind), int(block_threads)),
                    "pf_ensemble_tuning_set")
+
+
+def bandwidth_probe(nbytes=1 << 30, reps=5):
+    """Streaming HBM bandwidth of this device in GB/s: {"copy", "read", "multi"}."""
+    vals = [ctypes.c_double() for _ in range(3)]
+    _lib.check(_lib.lib().pf_bandwidth_probe(int(nbytes), int(reps), None, *[ctypes.byref(v) for v in vals]),
+               "pf_bandwidth_probe")
+    return dict(copy=vals[0].value, read=vals[1].value, multi=vals[2].value)
 
 
 def rel_l2(a, b):

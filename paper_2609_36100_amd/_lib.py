@@ -72,8 +72,8 @@ class Stats(ctypes.Structure):
 
 
 PF_FP64, PF_MIXED = 0, 1
-PF_IMEX_EULER, PF_ARK436L = 1, 4
-METHODS = {"imex_euler": PF_IMEX_EULER, "ark436l": PF_ARK436L}
+PF_IMEX_EULER, PF_ARK2, PF_ARK324L, PF_ARK436L = 1, 2, 3, 4
+METHODS = {"imex_euler": PF_IMEX_EULER, "ark2": PF_ARK2, "ark324l": PF_ARK324L, "ark436l": PF_ARK436L}
 PRECISIONS = {"fp64": PF_FP64, "mixed": PF_MIXED}
 
 _lib = None
@@ -147,6 +147,9 @@ _SIGS = {
     "pf_fno_advance": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
                                       ctypes.c_double, ctypes.c_int32, ctypes.c_double,
                                       ctypes.POINTER(FnoStats)]),
+    "pf_bandwidth_probe": (ctypes.c_int, [ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p,
+                                          ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                                          ctypes.POINTER(ctypes.c_double)]),
     "pf_rel_l2": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
                                  ctypes.POINTER(ctypes.c_double)]),
     "pf_profile_enable": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),

@@ -88,6 +88,83 @@ inline ArkTable table_ark436l() {
   return t;
 }
 
+// ARK2 of Giraldo, Kelly & Constantinescu (2013): three stages, second
+// order, gamma = 1 - 1/sqrt 2, explicit last-row weight (3 + 2 sqrt 2)/6,
+// first-order embedding.
+inline ArkTable table_ark2() {
+  ArkTable t;
+  std::memset(&t, 0, sizeof(t));
+  const double r2 = 1.41421356237309504880;
+  const double g = 1.0 - 1.0 / r2, d = 1.0 / (2.0 * r2), al = (3.0 + 2.0 * r2) / 6.0;
+  t.s = 3;
+  t.order = 2;
+  t.emb_order = 1;
+  t.has_emb = 1;
+  t.AE[1][0] = 2.0 * g;
+  t.AE[2][0] = 1.0 - al;
+  t.AE[2][1] = al;
+  t.AI[1][0] = g;
+  t.AI[1][1] = g;
+  t.AI[2][0] = d;
+  t.AI[2][1] = d;
+  t.AI[2][2] = g;
+  const double b[3] = {d, d, g};
+  const double bt[3] = {(4.0 - r2) / 8.0, (4.0 - r2) / 8.0, d};
+  for (int j = 0; j < 3; ++j) {
+    t.bE[j] = b[j];
+    t.bI[j] = b[j];
+    t.bt[j] = bt[j];
+  }
+  return t;
+}
+
+// ARK3(2)4L[2]SA (Kennedy & Carpenter 2003): published rational coefficients.
+inline ArkTable table_ark324l() {
+  ArkTable t;
+  std::memset(&t, 0, sizeof(t));
+  t.s = 4;
+  t.order = 3;
+  t.emb_order = 2;
+  t.has_emb = 1;
+  const double g = 1767732205903.0 / 4055673282236.0;
+  t.AE[1][0] = 1767732205903.0 / 2027836641118.0;
+  t.AE[2][0] = 5535828885825.0 / 10492691773637.0;
+  t.AE[2][1] = 788022342437.0 / 10882634858940.0;
+  t.AE[3][0] = 6485989280629.0 / 16251701735622.0;
+  t.AE[3][1] = -4246266847089.0 / 9704473918619.0;
+  t.AE[3][2] = 10755448449292.0 / 10357097424841.0;
+  t.AI[1][0] = 1767732205903.0 / 4055673282236.0;
+  t.AI[1][1] = g;
+  t.AI[2][0] = 2746238789719.0 / 10658868560708.0;
+  t.AI[2][1] = -640167445237.0 / 6845629431997.0;
+  t.AI[2][2] = g;
+  const double b[4] = {1471266399579.0 / 7840856788654.0, -4482444167858.0 / 7529755066697.0,
+                       11266239266428.0 / 11593286722821.0, 1767732205903.0 / 4055673282236.0};
+  const double bt[4] = {2756255671327.0 / 12835298489170.0, -10771552573575.0 / 22201958757719.0,
+                        9247589265047.0 / 10645013368117.0, 2193209047091.0 / 5459859503100.0};
+  for (int j = 0; j < 4; ++j) {
+    t.AI[3][j] = b[j];
+    t.bE[j] = b[j];
+    t.bI[j] = b[j];
+    t.bt[j] = bt[j];
+  }
+  return t;
+}
+
+// The table of a pf_method (IMEX Euler for an unknown value; callers validate).
+inline ArkTable table_for(int method) {
+  switch (method) {
+    case PF_ARK2: return table_ark2();
+    case PF_ARK324L: return table_ark324l();
+    case PF_ARK436L: return table_ark436l();
+    default: return table_imex_euler();
+  }
+}
+inline bool method_ok(int method) {
+  return method == PF_IMEX_EULER || method == PF_ARK2 || method == PF_ARK324L || method == PF_ARK436L;
+}
+inline bool method_embedded(int method) { return method == PF_ARK2 || method == PF_ARK324L || method == PF_ARK436L; }
+
 inline bool fe_needed(const ArkTable& t, int i) {
   if (t.bE[i] != 0.0 || (t.has_emb && t.bt[i] != 0.0)) return true;
   for (int k = i + 1; k < t.s; ++k)

@@ -603,7 +603,9 @@ pf_status pf_ensemble_init(int32_t n, const pf_params* per_member, void* stream,
   for (int m = 0; m < n; ++m) {
     const pf_params& p = per_member[m];
     if (p.nx != p.ny || p.ny != p.nz || !ens_size_ok(p.nx)) return PF_ERR_UNSUPPORTED_SIZE;
-    if (p.method != PF_ARK436L || p.precision != p0.precision || p.adaptive != p0.adaptive) return PF_ERR_ARG;
+    if (!method_embedded(p.method) || p.method != p0.method || p.precision != p0.precision ||
+        p.adaptive != p0.adaptive)
+      return PF_ERR_ARG;
     if (p.precision != PF_FP64 && p.precision != PF_MIXED) return PF_ERR_ARG;
     if (p.dx <= 0.0 || (p.adaptive && (p.rtol < 0.0 || p.atol <= 0.0))) return PF_ERR_ARG;
   }
@@ -621,7 +623,7 @@ pf_status pf_ensemble_init(int32_t n, const pf_params* per_member, void* stream,
     }
     E->own_stream = true;
   }
-  E->tab = table_ark436l();
+  E->tab = table_for(p0.method);
   for (int i = 0; i < 6; ++i) {
     E->fe_need[i] = fe_needed(E->tab, i);
     E->fi_need[i] = fi_needed(E->tab, i);

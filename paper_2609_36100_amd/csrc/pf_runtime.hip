@@ -495,6 +495,37 @@ static double controller(double dt, double err, int q, bool after_reject) {
 
 
 
+// ---- streaming-bandwidth probe kernels (measurement aid) ----------------------
+namespace {
+typedef double probe_d2 __attribute__((ext_vector_type(2)));
+__global__ void __launch_bounds__(256) k_probe_copy(const probe_d2* __restrict__ a, probe_d2* __restrict__ b,
+                                                    long long n) {
+  for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += 256LL * gridDim.x) b[i] = a[i];
+}
+__global__ void __launch_bounds__(256) k_probe_read(const probe_d2* __restrict__ a, long long n,
+                                                    double* __restrict__ sink) {
+  double s = 0.0;
+  for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += 256LL * gridDim.x) {
+    const probe_d2 v = a[i];
+    s += v.x + v.y;
+  }
+  if (s == -1.0) sink[0] = s;  // keeps the loads; never true for the zero-filled input
+}
+// eleven read streams and one write stream, the shape of the ARK4 update
+__global__ void __launch_bounds__(256) k_probe_multi(const probe_d2* __restrict__ a, probe_d2* __restrict__ b,
+                                                     long long n) {
+  for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += 256LL * gridDim.x) {
+    probe_d2 v[11];
+#pragma unroll
+    for (int k = 0; k < 11; ++k) v[k] = a[i + k * n];
+    probe_d2 acc = v[0];
+#pragma unroll
+    for (int k = 1; k < 11; ++k) acc += 0.5 * v[k];
+    b[i] = acc;
+  }
+}
+}  // namespace
+
 namespace pf {
 void ctx_setup(pf_ctx* c, const pf_params* p, hipStream_t stream) {
   c->p = *p;
@@ -517,7 +548,7 @@ void ctx_setup(pf_ctx* c, const pf_params* p, hipStream_t stream) {
   g.kfy = twopi / (p->ny * p->dx);
   g.kfz = twopi / (p->nz * p->dx);
   setup_model(c);
-  c->tab = p->method == PF_IMEX_EULER ? table_imex_euler() : table_ark436l();
+  c->tab = table_for(p->method);
   for (int i = 0; i < c->tab.s; ++i) {
     c->fe_need[i] = fe_needed(c->tab, i);
     c->fi_need[i] = fi_needed(c->tab, i);
@@ -532,6 +563,58 @@ void make_twiddles32(int n, cx<float>* host) { make_twiddles<float>(n, host); }
 
 // ---- C ABI ---------------------------------------------------------------------
 extern "C" {
+
+pf_status pf_bandwidth_probe(int64_t bytes, int32_t reps, void* stream, double* copy_gbs, double* read_gbs,
+                             double* multi_gbs) {
+  if (bytes < (1 << 20) || reps < 1) return PF_ERR_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  const long long n = bytes / 16;
+  probe_d2 *a = nullptr, *b = nullptr;
+  double* sink = nullptr;
+  if (hipMalloc((void**)&a, 11 * 16 * (size_t)n) != hipSuccess) return PF_ERR_OOM;
+  if (hipMalloc((void**)&b, 16 * (size_t)n) != hipSuccess || hipMalloc((void**)&sink, 8) != hipSuccess) {
+    hipFree(a);
+    hipFree(b);
+    return PF_ERR_OOM;
+  }
+  pf_status res = PF_OK;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipMemsetAsync(a, 0, 11 * 16 * (size_t)n, st) != hipSuccess || hipEventCreate(&e0) != hipSuccess ||
+      hipEventCreate(&e1) != hipSuccess)
+    res = PF_ERR_HIP;
+  const int grid = 1024;
+  auto best = [&](auto launch, double traffic) -> double {
+    double b_ms = 1e300;
+    launch();
+    for (int r = 0; r < reps && res == PF_OK; ++r) {
+      float ms = 0.f;
+      if (hipEventRecord(e0, st) != hipSuccess) res = PF_ERR_HIP;
+      launch();
+      if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+          hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+        res = PF_ERR_HIP;
+      if (ms > 0.f && ms < b_ms) b_ms = ms;
+    }
+    return traffic / (b_ms * 1e-3) / 1e9;
+  };
+  const double bb = 16.0 * n;
+  if (res == PF_OK) {
+    const double c = best([&] { k_probe_copy<<<grid, 256, 0, st>>>(a, b, n); }, 2 * bb);
+    const double r = best([&] { k_probe_read<<<grid, 256, 0, st>>>(a, n, sink); }, bb);
+    const double m = best([&] { k_probe_multi<<<grid, 256, 0, st>>>(a, b, n); }, 12 * bb);
+    if (hipGetLastError() != hipSuccess) res = PF_ERR_HIP;
+    if (copy_gbs) *copy_gbs = c;
+    if (read_gbs) *read_gbs = r;
+    if (multi_gbs) *multi_gbs = m;
+  }
+  if (e0) hipEventDestroy(e0);
+  if (e1) hipEventDestroy(e1);
+  hipStreamSynchronize(st);
+  hipFree(a);
+  hipFree(b);
+  hipFree(sink);
+  return res;
+}
 
 const char* pf_status_string(pf_status s) {
   switch (s) {
@@ -614,8 +697,8 @@ pf_status pf_init(const pf_params* p, void* stream, pf_ctx** out) {
   if (p->dx <= 0.0 || p->M < 0.0 || p->L < 0.0 || p->kappa_c < 0.0 || p->kappa_eta < 0.0)
     return PF_ERR_ARG;
   if (p->precision != PF_FP64 && p->precision != PF_MIXED) return PF_ERR_ARG;
-  if (p->method != PF_IMEX_EULER && p->method != PF_ARK436L) return PF_ERR_ARG;
-  if (p->adaptive && p->method != PF_ARK436L) return PF_ERR_ARG;
+  if (!method_ok(p->method)) return PF_ERR_ARG;
+  if (p->adaptive && !method_embedded(p->method)) return PF_ERR_ARG;
   if (p->adaptive && (p->rtol < 0.0 || p->atol <= 0.0)) return PF_ERR_ARG;
   if (p->mean_strain_mode != 0 && p->mean_strain_mode != 1) return PF_ERR_ARG;
   if (!pf_size_supported(p->nx) || !pf_size_supported(p->ny) || !pf_size_supported(p->nz))

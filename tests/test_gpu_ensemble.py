@@ -59,6 +59,25 @@ def test_fixed_step_ensemble_matches_oracle(torch, params, block_threads):
             assert st[m]["steps"] == [3, 2, 3][m] and st[m]["n_rhs"] == 6 * st[m]["steps"]
 
 
+@pytest.mark.parametrize("method,nrhs", [("ark2", 3), ("ark324l", 4)])
+def test_fixed_step_ensemble_lower_order_pairs(torch, params, method, nrhs):
+    """Batched members with the second- and third-order pairs match the oracle."""
+    from paper_2609_36100_amd import Ensemble
+    _say("ensemble fixed", method)
+    mem = _members([32, 48])
+    with Ensemble([dict(n=n, model=params, adaptive=False, dt0=0.1, method=method) for n, _, _ in mem]) as E:
+        for m, (n, c, eta) in enumerate(mem):
+            E.set_state(m, c, eta)
+        st = E.advance([0.3, 0.2])
+        for m, (n, c, eta) in enumerate(mem):
+            mdl = om.Model((n, n, n), params)
+            y = om.to_kspace(c, eta)
+            for _ in range([3, 2][m]):
+                y, _, _ = oark.ark_step(y, 0.1, oark.TABLES[method](), mdl.f_explicit, mdl.implicit_symbol())
+            assert _rel(E.get_state_hat(m), y) < TOL, m
+            assert st[m]["steps"] == [3, 2][m] and st[m]["n_rhs"] == nrhs * st[m]["steps"]
+
+
 def test_adaptive_ensemble_matches_single_runs(torch, params):
     from paper_2609_36100_amd import Ensemble, Solver
     _say("ensemble adaptive")

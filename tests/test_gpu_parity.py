@@ -215,6 +215,64 @@ def test_ark4_adaptive_replay_and_decisions(torch, params):
             assert _rel(g, yref) < TOL
 
 
+@pytest.mark.parametrize("method,nrhs", [("ark2", 3), ("ark324l", 4)])
+@pytest.mark.parametrize("n,dt,steps", [(16, 0.1, 3), (48, 0.05, 3)])
+def test_ark2_ark3_fixed_steps(torch, params, method, nrhs, n, dt, steps):
+    """The second- and third-order pairs: state, error estimate and RHS count per step."""
+    _say(method, "fixed", n, dt, steps)
+    spec, c, eta = pfinputs.config("small32", n=n)
+    m = om.Model((n, n, n), params)
+    y = om.to_kspace(c, eta)
+    t = oark.TABLES[method]()
+    L = m.implicit_symbol()
+    with _solver(n, params, method=method, dt0=dt) as s:
+        s.set_state(c, eta)
+        for k in range(steps):
+            y_old = y
+            y, lte, nexp = oark.ark_step(y, dt, t, m.f_explicit, L)
+            err_ref = oark.wrms_kspace(lte, y_old, 1e-6, 1e-9, m.mult, m.N3)
+            acc, err, _ = s.step(dt)
+            assert acc and nexp == nrhs
+            assert abs(err - err_ref) <= 1e-8 * err_ref, (err, err_ref)
+        g = s.kspace_to_numpy(s.get_state_hat())
+        for f in range(4):
+            assert _rel(g[f], y[f]) < TOL, (f, _rel(g[f], y[f]))
+        assert s.stats()["n_rhs"] == nrhs * steps
+
+
+@pytest.mark.parametrize("method", ["ark2", "ark324l"])
+def test_ark2_ark3_adaptive_replay_and_decisions(torch, params, method):
+    """Adaptive second- and third-order pairs at 32^3 (controller exponent
+    1/(q+1) with the embedding order q): oracle dt sequence replayed, then the
+    GPU controller's own decisions."""
+    _say(method, "adaptive 32^3")
+    n = 32
+    spec, c, eta = pfinputs.config("small32", n=n)
+    m = om.Model((n, n, n), params)
+    y0 = om.to_kspace(c, eta)
+    integ = oark.Integrator(m, table=method, adaptive=True, dt0=0.1, rtol=1e-5, atol=1e-8)
+    yref, tref = integ.advance(y0.copy(), 0.0, 2.0)
+    dts, errs = integ.stats["dts"], integ.stats["errs"]
+    with _solver(n, params, method=method, adaptive=False, rtol=1e-5, atol=1e-8) as s:
+        s.set_state(c, eta)
+        for dt, e in zip(dts, errs):
+            acc, err, _ = s.step(dt)
+            assert acc
+            assert abs(err - e) <= 1e-6 * e, (err, e)
+        g = s.kspace_to_numpy(s.get_state_hat())
+        assert _rel(g, yref) < TOL
+    near_one = any(abs(e - 1.0) < 1e-6 for e in errs)
+    with _solver(n, params, method=method, adaptive=True, dt0=0.1, rtol=1e-5, atol=1e-8) as s:
+        s.set_state(c, eta)
+        st = s.advance(2.0)
+        assert abs(st["t"] - 2.0) < 1e-12
+        if not near_one:
+            assert st["steps"] == integ.stats["steps"]
+            assert st["rejects"] == integ.stats["rejects"]
+            g = s.kspace_to_numpy(s.get_state_hat())
+            assert _rel(g, yref) < TOL
+
+
 @pytest.mark.parametrize("n", [32, 64])
 def test_mixed_precision_rhs_error_bound(torch, params, n):
     """FP32 FFT / pointwise / elastic work against the FP64 oracle: stated bound 1e-4 per field."""
