@@ -407,7 +407,7 @@ def orders_bench(torch, n, t_final):
                 return float(np.exp(np.log(w0) + f * (np.log(w1) - np.log(w0))))
         return None
     gains = {}
-    for target in (1e-4, 1e-5, 1e-6):
+    for target in (1e-7, 1e-8, 1e-9):
         w4 = cost_at("ark436l", target)
         row = {}
         for mth in ("imex_euler", "ark2", "ark324l"):

@@ -530,6 +530,8 @@ __device__ inline void body_zpass_elastic(cx<T>* th, const Geo& g, const ModelK&
   const long long base = (long long)y * g.P + x;
   auto buf = [&](int pos) -> cx<T>& { return lds[pos * CG::LD + col]; };
   cx<T> a[3][CG::R0];
+  // all three fields are loaded before the first transform (the registers are
+  // needed for the solve anyway), so their HBM latency is paid once
 #pragma unroll
   for (int v = 0; v < 3; ++v) {
 #pragma unroll
@@ -537,8 +539,9 @@ __device__ inline void body_zpass_elastic(cx<T>* th, const Geo& g, const ModelK&
       const int z = bf + t * CG::TL;
       a[v][t] = valid ? th[v * g.fs + base + z * lstride] : mk<T>(0, 0);
     }
-    line_fft<T, N, -1, RE>(a[v], bf, twz, buf, act);
   }
+#pragma unroll
+  for (int v = 0; v < 3; ++v) line_fft<T, N, -1, RE>(a[v], bf, twz, buf, act);
   const T kx = (T)(x * g.kfx);
   const T ky = (T)(mode_of(y, g.ny) * g.kfy);
 #pragma unroll
@@ -651,20 +654,26 @@ struct RowGeo {
   static constexpr int LD = M + 2;
 };
 
-// c2r of one half-spectrum row src[0..M] into real pairs a[t] = (x_{2n}, x_{2n+1}),
-// n = bf + t TL.  Unnormalised (full-spectrum sum).
+// The HBM reads of row_c2r on their own: raw[t] = src[bf + t TL], raw[R0] =
+// src[M] (bf == 0), so a caller can have them in flight during other work.
 template <typename T, int M, int RB>
-__device__ inline void row_c2r(const cx<T>* src, bool rvalid, cx<T>* a, int bf, cx<T>* rbuf,
-                               const cx<T>* twN, const cx<T>* twM, bool act = true) {
+__device__ inline void row_fetch(const cx<T>* src, bool rvalid, cx<T>* raw, int bf, bool act = true) {
+  using RG = RowGeo<M, RB>;
+#pragma unroll
+  for (int t = 0; t < RG::R0; ++t) raw[t] = (act && rvalid) ? src[bf + t * RG::TL] : mk<T>(0, 0);
+  raw[RG::R0] = (act && rvalid && bf == 0) ? src[M] : mk<T>(0, 0);
+}
+
+// row_c2r from values fetched by row_fetch.
+template <typename T, int M, int RB>
+__device__ inline void row_c2r_regs(const cx<T>* raw, cx<T>* a, int bf, cx<T>* rbuf, const cx<T>* twN,
+                                    const cx<T>* twM, bool act = true) {
   using RG = RowGeo<M, RB>;
   __syncthreads();
   if (act) {
 #pragma unroll
-    for (int t = 0; t < RG::R0; ++t) {
-      const int k = bf + t * RG::TL;
-      rbuf[k] = rvalid ? src[k] : mk<T>(0, 0);
-    }
-    if (bf == 0) rbuf[M] = rvalid ? src[M] : mk<T>(0, 0);
+    for (int t = 0; t < RG::R0; ++t) rbuf[bf + t * RG::TL] = raw[t];
+    if (bf == 0) rbuf[M] = raw[RG::R0];
   }
   __syncthreads();
   if (act) {
@@ -681,6 +690,17 @@ __device__ inline void row_c2r(const cx<T>* src, bool rvalid, cx<T>* a, int bf, 
     }
   }
   line_fft<T, M, +1>(a, bf, twM, [&](int pos) -> cx<T>& { return rbuf[pos]; }, act);
+}
+
+// c2r of one half-spectrum row src[0..M] into real pairs a[t] = (x_{2n}, x_{2n+1}),
+// n = bf + t TL.  Unnormalised (full-spectrum sum).
+template <typename T, int M, int RB>
+__device__ inline void row_c2r(const cx<T>* src, bool rvalid, cx<T>* a, int bf, cx<T>* rbuf,
+                               const cx<T>* twN, const cx<T>* twM, bool act = true) {
+  using RG = RowGeo<M, RB>;
+  cx<T> raw[RG::R0 + 1];
+  row_fetch<T, M, RB>(src, rvalid, raw, bf, act);
+  row_c2r_regs<T, M, RB>(raw, a, bf, rbuf, twN, twM, act);
 }
 
 // r2c of real pairs a[t] (n = bf + t TL) into half-spectrum row dst[0..M].
@@ -773,8 +793,11 @@ __device__ inline void body_xpass_drive(const cx<T>* st, cx<T>* el, const Geo& g
   }
   for (int v = 0; v < 3; ++v) {
     cx<T> et[RG::R0], a[RG::R0];
+    // both rows of this variant are requested before either is transformed
+    cx<T> raw_e[RG::R0 + 1];
+    row_fetch<T, M, RB>(el + v * g.fs + rb, rvalid, raw_e, bf, act);
     row_c2r<T, M, RB>(st + (1 + v) * g.fs + rb, rvalid, et, bf, rbuf, twN, twM, act);
-    row_c2r<T, M, RB>(el + v * g.fs + rb, rvalid, a, bf, rbuf, twN, twM, act);
+    row_c2r_regs<T, M, RB>(raw_e, a, bf, rbuf, twN, twM, act);
 #pragma unroll
     for (int t = 0; t < RG::R0; ++t) {
       const T e0 = et[t].re, e1 = et[t].im;

@@ -297,6 +297,37 @@ def test_mixed_precision_rhs_error_bound(torch, params, n):
         assert errs[f] < 1e-4
 
 
+def test_mixed_precision_twin64_run_error_per_field(torch, params):
+    """The precision form on the 64^3 twin of the 512^3 workload: adaptive
+    ARK4(3)6L at rtol 1e-5 in the FP64 oracle, its accepted steps replayed in
+    mixed precision on the GPU; the state error against the oracle is stated
+    per field (bound 1e-5 relative L2 over the run; c also in absolute terms)."""
+    _say("mixed twin64 run")
+    n = 64
+    spec, c, eta = pfinputs.config("twin64")
+    m = om.Model((n, n, n), params)
+    y0 = om.to_kspace(c, eta)
+    # diffuse the sharp nuclei first (oracle IMEX Euler), then about a dozen
+    # adaptive steps: the oracle needs ~1.3 s per ARK4 step at 64^3
+    for _ in range(20):
+        y0, _, _ = oark.ark_step(y0, 0.05, oark.imex_euler(), m.f_explicit, m.implicit_symbol())
+    integ = oark.Integrator(m, table="ark436l", adaptive=True, dt0=0.05, rtol=1e-5, atol=1e-8)
+    yref, _ = integ.advance(y0.copy(), 0.0, 0.25)
+    dts = integ.stats["dts"]
+    with _solver(n, params, method="ark436l", precision="mixed", rtol=1e-5, atol=1e-8) as s:
+        s.set_state_hat(s.kspace_from_numpy(y0))
+        for dt in dts:
+            acc, _, _ = s.step(dt)
+            assert acc
+        g = s.kspace_to_numpy(s.get_state_hat())
+    errs = [_rel(g[f], yref[f]) for f in range(4)]
+    print("mixed twin64: %d steps, per-field rel-L2 %s" % (len(dts), ["%.2e" % e for e in errs]), flush=True)
+    for f in range(4):
+        assert errs[f] < 1e-5, (f, errs[f])
+    # mass mode: FP64 stage sums keep it exact
+    assert abs(g[0, 0, 0, 0] - yref[0, 0, 0, 0]) <= 1e-12 * abs(yref[0, 0, 0, 0])
+
+
 @pytest.mark.parametrize("shape", [(64, 64, 64), (96, 96, 96), (128, 64, 96), (128, 128, 128), (160, 128, 96)])
 @pytest.mark.parametrize("variant", [0, 1, 2])
 def test_tile_variants_match_oracle(torch, params, shape, variant):
