@@ -530,8 +530,10 @@ __device__ inline void body_zpass_elastic(cx<T>* th, const Geo& g, const ModelK&
   const long long base = (long long)y * g.P + x;
   auto buf = [&](int pos) -> cx<T>& { return lds[pos * CG::LD + col]; };
   cx<T> a[3][CG::R0];
-  // all three fields are loaded before the first transform (the registers are
-  // needed for the solve anyway), so their HBM latency is paid once
+  // FP32: all three fields are loaded before the first transform, so their
+  // HBM latency is paid once (measured 4.6% faster at 512^3); FP64: field by
+  // field (3% faster: the early loads lengthen the first transform there)
+  constexpr bool hoist = sizeof(T) == 4;
 #pragma unroll
   for (int v = 0; v < 3; ++v) {
 #pragma unroll
@@ -539,9 +541,12 @@ __device__ inline void body_zpass_elastic(cx<T>* th, const Geo& g, const ModelK&
       const int z = bf + t * CG::TL;
       a[v][t] = valid ? th[v * g.fs + base + z * lstride] : mk<T>(0, 0);
     }
+    if constexpr (!hoist) line_fft<T, N, -1, RE>(a[v], bf, twz, buf, act);
   }
+  if constexpr (hoist) {
 #pragma unroll
-  for (int v = 0; v < 3; ++v) line_fft<T, N, -1, RE>(a[v], bf, twz, buf, act);
+    for (int v = 0; v < 3; ++v) line_fft<T, N, -1, RE>(a[v], bf, twz, buf, act);
+  }
   const T kx = (T)(x * g.kfx);
   const T ky = (T)(mode_of(y, g.ny) * g.kfy);
 #pragma unroll
@@ -665,17 +670,18 @@ __device__ inline void row_fetch(const cx<T>* src, bool rvalid, cx<T>* raw, int 
 }
 
 // row_c2r from values fetched by row_fetch.
-template <typename T, int M, int RB>
+// LB: LDS-only barriers (global loads and stores stay in flight across them).
+template <typename T, int M, int RB, bool LB = false>
 __device__ inline void row_c2r_regs(const cx<T>* raw, cx<T>* a, int bf, cx<T>* rbuf, const cx<T>* twN,
                                     const cx<T>* twM, bool act = true) {
   using RG = RowGeo<M, RB>;
-  __syncthreads();
+  xbar<LB>();
   if (act) {
 #pragma unroll
     for (int t = 0; t < RG::R0; ++t) rbuf[bf + t * RG::TL] = raw[t];
     if (bf == 0) rbuf[M] = raw[RG::R0];
   }
-  __syncthreads();
+  xbar<LB>();
   if (act) {
 #pragma unroll
     for (int t = 0; t < RG::R0; ++t) {
@@ -689,7 +695,7 @@ __device__ inline void row_c2r_regs(const cx<T>* raw, cx<T>* a, int bf, cx<T>* r
       a[t] = c2r_pre(xk, xmk, twN[k]);
     }
   }
-  line_fft<T, M, +1>(a, bf, twM, [&](int pos) -> cx<T>& { return rbuf[pos]; }, act);
+  line_fft<T, M, +1, 8, LB>(a, bf, twM, [&](int pos) -> cx<T>& { return rbuf[pos]; }, act);
 }
 
 // c2r of one half-spectrum row src[0..M] into real pairs a[t] = (x_{2n}, x_{2n+1}),
@@ -704,17 +710,17 @@ __device__ inline void row_c2r(const cx<T>* src, bool rvalid, cx<T>* a, int bf, 
 }
 
 // r2c of real pairs a[t] (n = bf + t TL) into half-spectrum row dst[0..M].
-template <typename T, int M, int RB>
+template <typename T, int M, int RB, bool LB = false>
 __device__ inline void row_r2c(cx<T>* a, cx<T>* dst, bool rvalid, int bf, cx<T>* rbuf,
                                const cx<T>* twN, const cx<T>* twM, bool act = true) {
   using RG = RowGeo<M, RB>;
-  line_fft<T, M, -1>(a, bf, twM, [&](int pos) -> cx<T>& { return rbuf[pos]; }, act);
-  __syncthreads();
+  line_fft<T, M, -1, 8, LB>(a, bf, twM, [&](int pos) -> cx<T>& { return rbuf[pos]; }, act);
+  xbar<LB>();
   if (act) {
 #pragma unroll
     for (int t = 0; t < RG::R0; ++t) rbuf[bf + t * RG::TL] = a[t];
   }
-  __syncthreads();
+  xbar<LB>();
   if (act && rvalid) {
 #pragma unroll
     for (int t = 0; t < RG::R0; ++t) {
@@ -759,12 +765,35 @@ __device__ inline void body_xpass_theta(const cx<T>* st, cx<T>* th, const Geo& g
   }
 }
 
+// Single-grid theta pass, software-pipelined: the rows of eta_{v+1} are
+// requested before eta_v's transform back, and stay in flight across its
+// exchanges (LDS-only barriers; the line-FFT twiddles are copied to LDS so
+// that no global load issued after the prefetch has to wait for it).
 template <typename T, int M, int RB>
 __global__ void __launch_bounds__((RowGeo<M, RB>::THREADS))
 k_xpass_theta(const cx<T>* __restrict__ st, cx<T>* __restrict__ th, Geo g, const cx<T>* twN,
               const cx<T>* twM) {
-  __shared__ cx<T> lds[RB * RowGeo<M, RB>::LD];
-  body_xpass_theta<T, M, RB>(st, th, g, twN, twM, blockIdx.x, threadIdx.x, lds);
+  using RG = RowGeo<M, RB>;
+  __shared__ cx<T> lds[RB * RG::LD];
+  __shared__ cx<T> tM[M];
+  for (int j = threadIdx.x; j < M; j += RG::THREADS) tM[j] = twM[j];
+  const int rl = threadIdx.x / RG::TL;
+  const int bf = threadIdx.x % RG::TL;
+  const int row = blockIdx.x * RB + rl;
+  const bool rvalid = row < g.nz * g.ny;
+  cx<T>* rbuf = lds + rl * RG::LD;
+  const long long rb = (long long)(rvalid ? row : 0) * g.P;
+  cx<T> raw[RG::R0 + 1];
+  row_fetch<T, M, RB>(st + g.fs + rb, rvalid, raw, bf);
+#pragma unroll 1
+  for (int v = 0; v < 3; ++v) {
+    cx<T> a[RG::R0];
+    row_c2r_regs<T, M, RB, true>(raw, a, bf, rbuf, twN, tM);
+    if (v < 2) row_fetch<T, M, RB>(st + (2 + v) * g.fs + rb, rvalid, raw, bf);
+#pragma unroll
+    for (int t = 0; t < RG::R0; ++t) a[t] = mk<T>(hfun(a[t].re), hfun(a[t].im));
+    row_r2c<T, M, RB, true>(a, th + v * g.fs + rb, rvalid, bf, rbuf, twN, tM);
+  }
 }
 
 // K-G: g_v = h'(eta_v) (chi(c) + e_v) + 2 w eta_v (1 - eta_v)(1 - 2 eta_v).
@@ -793,11 +822,17 @@ __device__ inline void body_xpass_drive(const cx<T>* st, cx<T>* el, const Geo& g
   }
   for (int v = 0; v < 3; ++v) {
     cx<T> et[RG::R0], a[RG::R0];
-    // both rows of this variant are requested before either is transformed
-    cx<T> raw_e[RG::R0 + 1];
-    row_fetch<T, M, RB>(el + v * g.fs + rb, rvalid, raw_e, bf, act);
-    row_c2r<T, M, RB>(st + (1 + v) * g.fs + rb, rvalid, et, bf, rbuf, twN, twM, act);
-    row_c2r_regs<T, M, RB>(raw_e, a, bf, rbuf, twN, twM, act);
+    if constexpr (sizeof(T) == 8) {
+      // FP64: both rows of this variant are requested before either is
+      // transformed (8% faster at 512^3; 8% slower in FP32, kept apart there)
+      cx<T> raw_e[RG::R0 + 1];
+      row_fetch<T, M, RB>(el + v * g.fs + rb, rvalid, raw_e, bf, act);
+      row_c2r<T, M, RB>(st + (1 + v) * g.fs + rb, rvalid, et, bf, rbuf, twN, twM, act);
+      row_c2r_regs<T, M, RB>(raw_e, a, bf, rbuf, twN, twM, act);
+    } else {
+      row_c2r<T, M, RB>(st + (1 + v) * g.fs + rb, rvalid, et, bf, rbuf, twN, twM, act);
+      row_c2r<T, M, RB>(el + v * g.fs + rb, rvalid, a, bf, rbuf, twN, twM, act);
+    }
 #pragma unroll
     for (int t = 0; t < RG::R0; ++t) {
       const T e0 = et[t].re, e1 = et[t].im;
@@ -809,12 +844,65 @@ __device__ inline void body_xpass_drive(const cx<T>* st, cx<T>* el, const Geo& g
   }
 }
 
+// Single-grid driving-force pass, software-pipelined like the theta pass (FP32):
+// the eta row of variant v + 1 is requested before variant v's transform back
+// and stays in flight across its exchanges; the elastic-potential row of
+// variant v + 1 is requested after that transform and stays in flight across
+// the eta row's transform (the first eta row with the composition row, the
+// first elastic row after the composition row's transform).
 template <typename T, int M, int RB>
 __global__ void __launch_bounds__((RowGeo<M, RB>::THREADS))
 k_xpass_drive(const cx<T>* __restrict__ st, cx<T>* __restrict__ el, Geo g, ModelK m, const cx<T>* twN,
               const cx<T>* twM) {
-  __shared__ cx<T> lds[RB * RowGeo<M, RB>::LD];
-  body_xpass_drive<T, M, RB>(st, el, g, m, twN, twM, blockIdx.x, threadIdx.x, lds);
+  using RG = RowGeo<M, RB>;
+  __shared__ cx<T> lds[RB * RG::LD];
+  if constexpr (sizeof(T) == 8) {
+    // FP64: the prefetch registers would cut the occupancy from 3 to 2 waves
+    // per SIMD; the plain body is used
+    body_xpass_drive<T, M, RB>(st, el, g, m, twN, twM, blockIdx.x, threadIdx.x, lds);
+    return;
+  }
+  __shared__ cx<T> tM[M];
+  for (int j = threadIdx.x; j < M; j += RG::THREADS) tM[j] = twM[j];
+  const int rl = threadIdx.x / RG::TL;
+  const int bf = threadIdx.x % RG::TL;
+  const int row = blockIdx.x * RB + rl;
+  const bool rvalid = row < g.nz * g.ny;
+  cx<T>* rbuf = lds + rl * RG::LD;
+  const long long rb = (long long)(rvalid ? row : 0) * g.P;
+  const T W = (T)m.W, cm = (T)m.cm, cp = (T)m.cp, w2 = (T)(2.0 * m.w);
+  cx<T> raw_eta[RG::R0 + 1], raw_e[RG::R0 + 1];
+  cx<T> chi[RG::R0];
+  {
+    cx<T> raw_c[RG::R0 + 1];
+    row_fetch<T, M, RB>(st + rb, rvalid, raw_c, bf);
+    row_fetch<T, M, RB>(st + g.fs + rb, rvalid, raw_eta, bf);
+    cx<T> a[RG::R0];
+    row_c2r_regs<T, M, RB, true>(raw_c, a, bf, rbuf, twN, tM);
+    row_fetch<T, M, RB>(el + rb, rvalid, raw_e, bf);
+#pragma unroll
+    for (int t = 0; t < RG::R0; ++t) {
+      const T c0 = a[t].re, c1 = a[t].im;
+      chi[t] = mk<T>(W * ((c0 - cp) * (c0 - cp) - (c0 - cm) * (c0 - cm)),
+                     W * ((c1 - cp) * (c1 - cp) - (c1 - cm) * (c1 - cm)));
+    }
+  }
+#pragma unroll 1
+  for (int v = 0; v < 3; ++v) {
+    cx<T> et[RG::R0], a[RG::R0];
+    row_c2r_regs<T, M, RB, true>(raw_eta, et, bf, rbuf, twN, tM);
+    row_c2r_regs<T, M, RB, true>(raw_e, a, bf, rbuf, twN, tM);
+    if (v < 2) row_fetch<T, M, RB>(st + (2 + v) * g.fs + rb, rvalid, raw_eta, bf);
+#pragma unroll
+    for (int t = 0; t < RG::R0; ++t) {
+      const T e0 = et[t].re, e1 = et[t].im;
+      const T g0 = dhfun(e0) * (chi[t].re + a[t].re) + w2 * e0 * ((T)1 - e0) * ((T)1 - (T)2 * e0);
+      const T g1 = dhfun(e1) * (chi[t].im + a[t].im) + w2 * e1 * ((T)1 - e1) * ((T)1 - (T)2 * e1);
+      a[t] = mk<T>(g0, g1);
+    }
+    row_r2c<T, M, RB, true>(a, el + v * g.fs + rb, rvalid, bf, rbuf, twN, tM);
+    if (v < 2) row_fetch<T, M, RB>(el + (1 + v) * g.fs + rb, rvalid, raw_e, bf);
+  }
 }
 
 // Standalone row r2c: real rows (length 2M, pitch 2M) -> half-spectrum rows.
