@@ -398,11 +398,59 @@ __device__ inline void body_colfft(const cx<T>* in, cx<T>* out, const Geo& g, in
   }
 }
 
+// Column passes over several fields, software-pipelined: field f + 1 is
+// loaded into registers while field f is transformed (LDS-only barriers,
+// twiddles in LDS, so the loads stay in flight across the exchanges).  Used
+// in FP32, where the second register set costs no occupancy; FP64 keeps the
+// field-by-field body (it would drop from two work-groups per CU to one).
+template <typename T, int N, int TX, int RE, int S, class LoadF, class StoreF>
+__device__ inline void colfft_pipelined(int nf, int bf, bool valid, const cx<T>* twl, cx<T>* lds, int col,
+                                        LoadF load, StoreF store) {
+  using CG = ColGeo<N, TX, RE>;
+  auto buf = [&](int pos) -> cx<T>& { return lds[pos * CG::LD + col]; };
+  cx<T> a[CG::R0], b[CG::R0];
+#pragma unroll
+  for (int t = 0; t < CG::R0; ++t) a[t] = valid ? load(0, bf + t * CG::TL) : mk<T>(0, 0);
+#pragma unroll 1
+  for (int f = 0; f < nf; ++f) {
+    if (f + 1 < nf) {
+#pragma unroll
+      for (int t = 0; t < CG::R0; ++t) b[t] = valid ? load(f + 1, bf + t * CG::TL) : mk<T>(0, 0);
+    }
+    line_fft<T, N, S, RE, true>(a, bf, twl, buf, true);
+    if (valid) {
+#pragma unroll
+      for (int t = 0; t < CG::R0; ++t) store(f, bf + t * CG::TL, a[t]);
+    }
+#pragma unroll
+    for (int t = 0; t < CG::R0; ++t) a[t] = b[t];
+  }
+}
+
 template <typename T, int N, int TX, int RE, int S, int AXIS>
 __global__ void __launch_bounds__((ColGeo<N, TX, RE>::THREADS))
 k_colfft(const cx<T>* in, cx<T>* out, Geo g, int nf, const cx<T>* tw, T scale) {
-  __shared__ cx<T> lds[N * ColGeo<N, TX, RE>::LD];
-  body_colfft<T, N, TX, RE, S, AXIS>(in, out, g, nf, tw, scale, xcd_tile(blockIdx.x, gridDim.x), threadIdx.x, lds);
+  using CG = ColGeo<N, TX, RE>;
+  __shared__ cx<T> lds[N * CG::LD];
+  if constexpr (sizeof(T) == 8) {
+    body_colfft<T, N, TX, RE, S, AXIS>(in, out, g, nf, tw, scale, xcd_tile(blockIdx.x, gridDim.x), threadIdx.x,
+                                       lds);
+  } else {
+    __shared__ cx<T> twl[N];
+    for (int j = threadIdx.x; j < N; j += CG::THREADS) twl[j] = tw[j];
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int nbx = (g.nxh + TX - 1) / TX;
+    const int xb = tile % nbx;
+    const int o = tile / nbx;
+    const int col = threadIdx.x % TX;
+    const int bf = threadIdx.x / TX;
+    const int x = xb * TX + col;
+    const long long lstride = AXIS == 1 ? (long long)g.P : (long long)g.ny * g.P;
+    const long long base = AXIS == 1 ? (long long)o * g.ny * g.P + x : (long long)o * g.P + x;
+    colfft_pipelined<T, N, TX, RE, S>(
+        nf, bf, x < g.nxh, twl, lds, col, [&](int f, int q) { return in[f * g.fs + base + q * lstride]; },
+        [&](int f, int q, cx<T> v) { out[f * g.fs + base + q * lstride] = scale * v; });
+  }
 }
 
 // ---- wave-specialised column FFT (persistent) ------------------------------
@@ -646,8 +694,30 @@ __device__ inline void body_zpass_fwd_ac(const cx<T>* gk, const Geo& g, const Mo
 template <typename T, typename TE, int N, int TX, int RE>
 __global__ void __launch_bounds__((ColGeo<N, TX, RE>::THREADS))
 k_zpass_fwd_ac(const cx<T>* __restrict__ gk, Geo g, ModelK m, const cx<T>* twz, cx<TE>* __restrict__ FE) {
-  __shared__ cx<T> lds[N * ColGeo<N, TX, RE>::LD];
-  body_zpass_fwd_ac<T, TE, N, TX, RE>(gk, g, m, twz, FE, xcd_tile(blockIdx.x, gridDim.x), threadIdx.x, lds);
+  using CG = ColGeo<N, TX, RE>;
+  __shared__ cx<T> lds[N * CG::LD];
+  if constexpr (sizeof(T) == 8) {
+    body_zpass_fwd_ac<T, TE, N, TX, RE>(gk, g, m, twz, FE, xcd_tile(blockIdx.x, gridDim.x), threadIdx.x, lds);
+  } else {
+    __shared__ cx<T> twl[N];
+    for (int j = threadIdx.x; j < N; j += CG::THREADS) twl[j] = twz[j];
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int nbx = (g.nxh + TX - 1) / TX;
+    const int xb = tile % nbx;
+    const int y = tile / nbx;
+    const int col = threadIdx.x % TX;
+    const int bf = threadIdx.x / TX;
+    const int x = xb * TX + col;
+    const long long lstride = (long long)g.ny * g.P;
+    const long long base = (long long)y * g.P + x;
+    const T nl = (T)(-m.L);
+    colfft_pipelined<T, N, TX, RE, -1>(
+        3, bf, x < g.nxh, twl, lds, col, [&](int f, int z) { return gk[f * g.fs + base + z * lstride]; },
+        [&](int f, int z, cx<T> v) {
+          const cx<T> r = nl * v;
+          FE[(1 + f) * g.fs + base + z * lstride] = mk<TE>((TE)r.re, (TE)r.im);
+        });
+  }
 }
 
 // ---- row (x-axis) passes ---------------------------------------------------
