@@ -418,6 +418,51 @@ def orders_bench(torch, n, t_final):
     return out
 
 
+def fno_step_bench(torch, n=128, reps=10):
+    """The surrogate's kernels on their own: one training step (forward, loss,
+    backward) and one surrogate advance at n^3 (width 32, 12 modes, 4 layers),
+    with the dense-contraction flops they carry."""
+    import numpy as np
+    from paper_2609_36100_amd import surrogate as sg
+    f = sg.make_fno(n, 32, 12, 4, 128, seed=0, scale=np.full(4, 1e-3, np.float32))
+    g = torch.Generator(device="cuda").manual_seed(0)
+    x = torch.rand((4, n, n, n), dtype=torch.float32, device="cuda", generator=g)
+    y = x + 1e-3 * torch.rand((4, n, n, n), dtype=torch.float32, device="cuda", generator=g)
+    u = x.double().contiguous()
+    w = torch.empty_like(u)
+    for _ in range(2):
+        f.grad(x, y)
+        f.apply(u, w)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        f.grad(x, y)
+    torch.cuda.synchronize()
+    t_grad = (time.perf_counter() - t0) / reps
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        f.adam_step(1e-4)
+    torch.cuda.synchronize()
+    t_adam = (time.perf_counter() - t0) / reps
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        f.apply(u, w)
+    torch.cuda.synchronize()
+    t_apply = (time.perf_counter() - t0) / reps
+    # flops of one forward pass (channel counts padded to 8 as the kernels run
+    # them): lift; per layer the pointwise W, the six truncated-DFT GEMM
+    # stages (x: 4 m w n^3 each way, y: 16 m^2 w n^2, z: 32 m^3 w n) and the
+    # per-mode complex w x w mixing (32 m^3 w^2); projection
+    P = n ** 3
+    wd, m, L, h = 32, 12, 4, 128
+    layer = 2 * P * wd * wd + 2 * (4 * m * wd * n ** 3 + 16 * m * m * wd * n * n + 32 * m ** 3 * wd * n) \
+        + 32 * m ** 3 * wd * wd
+    fwd = 2 * P * 8 * wd + L * layer + 2 * P * wd * h + 2 * P * h * 8
+    return dict(n=n, grad_ms=round(1e3 * t_grad, 3), adam_ms=round(1e3 * t_adam, 3), apply_ms=round(1e3 * t_apply, 3),
+                forward_gflop=round(fwd / 1e9, 2),
+                apply_tflops=round(fwd / t_apply / 1e12, 2))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -428,7 +473,8 @@ def main():
     ap.add_argument("--skip-mixed", action="store_true")
     ap.add_argument("--skip-fft", action="store_true")
     ap.add_argument("--skip-cpu", action="store_true")
-    ap.add_argument("--mode", choices=["throughput", "ensemble", "time_to_t", "fno", "orders"], default="throughput")
+    ap.add_argument("--mode", choices=["throughput", "ensemble", "time_to_t", "fno", "fno_step", "orders"],
+                    default="throughput")
     ap.add_argument("--runs", type=int, default=40, help="fno: training runs")
     ap.add_argument("--val-runs", type=int, default=4, help="fno: held-out runs")
     ap.add_argument("--snapshots", type=int, default=50, help="fno: snapshots per run")
@@ -484,6 +530,15 @@ def main():
                                                  "uneven ensemble's 128^3 members, to t=%g, checks every 5th "
                                                  "advance at rel-L2(c) 1e-3" % g["t_final"]},
                           "fno": r}), flush=True)
+        return
+    if args.mode == "fno_step":
+        r = fno_step_bench(torch, args.n if args.n != 512 else 128)
+        print(json.dumps({"metric": METRIC, "mode": "fno_step", "unit": "ms", "value": r["grad_ms"],
+                          "higher_is_better": False, "n_gpus": 1, "dtype": "bf16 (fp32 accumulate)",
+                          "data": "synthetic",
+                          "config": {"workload": "FNO (4 layers, width 32, 12 modes, hidden 128) at %d^3: one "
+                                                 "training step and one surrogate advance" % r["n"]},
+                          "fno_step": r}), flush=True)
         return
     if args.mode == "orders":
         n = args.n if args.n != 512 else 128
