@@ -103,14 +103,18 @@ k_cm_gemm(const u16* __restrict__ In, int ldin, int K, const u16* __restrict__ B
 // ---- small-matrix GEMM: Out_b[r][n] = sum_k G[r][k] X_b[k][n] ---------------
 // G row-major R x K (K % 4 == 0, zero beyond K), X_b rows of stride ldx,
 // batch stride xbs.
-// Each wave owns 32 columns and 4 row tiles (128 rows) per pass.
+// Each wave owns 32 columns and 4 row tiles (128 rows) per pass.  A block's
+// four waves cover wpb column groups of `bpb = 4 / wpb` batches (wpb = 1 for
+// the 32-column x stages, so no wave of a block idles there).
 __global__ void __launch_bounds__(256)
 k_lm_gemm(const u16* __restrict__ G, int R, int K, const u16* __restrict__ X, long long xbs, int ldx, int Nc,
-          float* __restrict__ outf, u16* __restrict__ outb, long long obs, int ldo, int accumulate) {
+          float* __restrict__ outf, u16* __restrict__ outb, long long obs, int ldo, int accumulate, int wpb,
+          long long batches) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int lr = lane & 31, lg = lane >> 5;
-  const long long b = blockIdx.y;
-  const int n = (blockIdx.x * 4 + wave) * 32 + lr;
+  const long long b = (long long)blockIdx.y * (4 / wpb) + wave / wpb;
+  if (b >= batches) return;  // no block-level synchronisation in this kernel
+  const int n = (blockIdx.x * wpb + wave % wpb) * 32 + lr;
   const bool valid = n < Nc;
   const u16* Xb = X + b * xbs;
   for (int r0 = 0; r0 < R; r0 += 128) {
@@ -214,10 +218,10 @@ k_mix_bwd_w(const float* __restrict__ S, const float* __restrict__ dT, float* __
 // so each block stages WG_PTS points of A (bf16) and D (f32, rounded to bf16)
 // transposed into LDS ([channel][point], padded rows) and every wave feeds
 // 32 of those points to v_mfma_f32_32x32x8bf16_1k for up to four 32 x 32
-// output tiles [t0, t0 + 4) of the ceil(K/32) x ceil(N/32) tile grid.  Each
-// wave writes its partial tiles to part[(block * 4 + wave) * KN + k * N + n]
-// (KN = (K + 1) * N; row k = K holds the bias sums, written by wave 0 when
-// t0 == 0); k_sum_partials adds the sets.  Requires lda % 4 == 0, K <= lda,
+// output tiles [t0, t0 + 4) of the ceil(K/32) x ceil(N/32) tile grid.  The
+// four waves' tiles are summed in LDS and each block writes one partial set
+// part[block * KN + k * N + n] (KN = (K + 1) * N; row k = K holds the bias
+// sums, written when t0 == 0); k_sum_partials adds the sets.  Requires lda % 4 == 0, K <= lda,
 // channels K .. 4 ceil(K/4) of A zero, K, N <= 128, chunk % WG_PTS == 0.
 constexpr int WG_PTS = 128;
 constexpr int WG_LD = WG_PTS + 4;  // bf16 row pitch: 264 B rows keep the 8-byte MFMA reads spread over banks
@@ -225,8 +229,11 @@ constexpr int WG_LD = WG_PTS + 4;  // bf16 row pitch: 264 B rows keep the 8-byte
 __global__ void __launch_bounds__(256)
 k_wgrad_mfma(const u16* __restrict__ A, int lda, int K, const float* __restrict__ D, int ldd, int N, long long P,
              int chunk, int t0, float* __restrict__ part) {
-  __shared__ __attribute__((aligned(16))) u16 LA[128 * WG_LD];
-  __shared__ __attribute__((aligned(16))) u16 LD[128 * WG_LD];
+  // one buffer: the staged operands LA [k][p] and LD [n][p], reused at the end
+  // for the cross-wave sum of the partial tiles (4 waves x 4 tiles x 1024 floats)
+  __shared__ __attribute__((aligned(16))) u16 smem[2 * 128 * WG_LD];
+  u16* LA = smem;
+  u16* LD = smem + 128 * WG_LD;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, lr = lane & 31, lg = lane >> 5;
   const int Nt = (N + 31) / 32;
   const int ntiles = min(4, ((K + 31) / 32) * Nt - t0);
@@ -276,44 +283,55 @@ k_wgrad_mfma(const u16* __restrict__ A, int lda, int K, const float* __restrict_
       }
     }
   }
-  float* dst = part + ((long long)blockIdx.x * 4 + wave) * KN;
+  // sum the four waves' tiles in LDS, then one partial set per block
+  __syncthreads();
+  float* red = reinterpret_cast<float*>(smem);
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
     if (t >= ntiles) break;
-    const int tile = t0 + t, kt = tile / Nt, nt = tile % Nt;
-    const int n = nt * 32 + lr;
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
-      const int k = kt * 32 + 8 * (i >> 2) + 4 * lg + (i & 3);
-      if (k < K && n < N) dst[k * N + n] = acc[t][i];
+      const int row = 8 * (i >> 2) + 4 * lg + (i & 3);
+      red[(wave * 4 + t) * 1024 + row * 32 + lr] = acc[t][i];
     }
   }
-  if (t0 == 0 && tid < N) {
-    // the bias row: block sum in wave 0's set, zero in the others
-    for (int w = 0; w < 4; ++w) part[((long long)blockIdx.x * 4 + w) * KN + K * N + tid] = w == 0 ? bsum : 0.f;
+  __syncthreads();
+  float* dst = part + (long long)blockIdx.x * KN;
+  for (int e = tid; e < ntiles * 1024; e += 256) {
+    const int t = e >> 10, w = e & 1023;
+    const int tile = t0 + t, kt = tile / Nt, nt = tile % Nt;
+    const int k = kt * 32 + (w >> 5), n = nt * 32 + (w & 31);
+    if (k < K && n < N)
+      dst[k * N + n] = (red[t * 1024 + w] + red[(4 + t) * 1024 + w]) +
+                       (red[(8 + t) * 1024 + w] + red[(12 + t) * 1024 + w]);
   }
+  if (t0 == 0 && tid < N) dst[K * N + tid] = bsum;  // the bias row
 }
 
 // Adds nsets partial sets into gW / gb, for the entries of tiles [t0, t0 + 4)
-// (and the bias row when t0 == 0).
+// (and the bias row when t0 == 0).  A block sums 64 consecutive entries: its
+// four groups of 64 threads take every fourth set, then combine in LDS.
 __global__ void __launch_bounds__(256) k_sum_partials(const float* __restrict__ part, int nsets, int K, int N,
                                                       int t0, float* __restrict__ gW, float* __restrict__ gb) {
+  __shared__ float sh[4][64];
   const int KN = (K + 1) * N;
-  const int e = blockIdx.x * 256 + threadIdx.x;
-  if (e >= KN) return;
+  const int el = threadIdx.x & 63, grp = threadIdx.x >> 6;
+  const int e = blockIdx.x * 64 + el;
+  float s = 0.f;
+  if (e < KN)
+    for (int b = grp; b < nsets; b += 4) s += part[(long long)b * KN + e];
+  sh[grp][el] = s;
+  __syncthreads();
+  if (grp != 0 || e >= KN) return;
+  s = (sh[0][el] + sh[1][el]) + (sh[2][el] + sh[3][el]);
   const int k = e / N, n = e % N;
   if (k < K) {
     const int tile = (k / 32) * ((N + 31) / 32) + n / 32;
     if (tile < t0 || tile >= t0 + 4) return;
-  } else if (t0 != 0) {
-    return;
-  }
-  float s = 0.f;
-  for (int b = 0; b < nsets; ++b) s += part[(long long)b * KN + e];
-  if (k < K)
     gW[k * N + n] += s;
-  else
+  } else if (t0 == 0) {
     gb[n] += s;
+  }
 }
 
 // ---- elementwise ------------------------------------------------------------------
@@ -574,8 +592,10 @@ static pf_status upload_bf16(pf_fno* F, const std::vector<float>& h, u16** d) {
 
 static void lm(pf_fno* F, const u16* G, int R, int K, const u16* X, long long xbs, int ldx, int Nc, int batches,
                float* outf, u16* outb, long long obs, int ldo, int accumulate) {
-  dim3 grid(gdiv(Nc, 128), batches);
-  k_lm_gemm<<<grid, 256, 0, F->stream>>>(G, R, K, X, xbs, ldx, Nc, outf, outb, obs, ldo, accumulate);
+  const int wpb = Nc <= 32 ? 1 : (Nc <= 64 ? 2 : 4);  // waves per batch
+  dim3 grid(gdiv(Nc, 32 * wpb), gdiv(batches, 4 / wpb));
+  k_lm_gemm<<<grid, 256, 0, F->stream>>>(G, R, K, X, xbs, ldx, Nc, outf, outb, obs, ldo, accumulate, wpb,
+                                         (long long)batches);
 }
 
 static void cm(pf_fno* F, const u16* In, int ldin, int K, const u16* Bt, int N, const float* bias, const float* resid,
@@ -589,7 +609,7 @@ static void cm(pf_fno* F, const u16* In, int ldin, int K, const u16* Bt, int N, 
                                                accumulate);
 }
 
-constexpr int kWgradBlocks = 256;  // blocks (point chunks) of one weight-gradient reduction
+constexpr int kWgradBlocks = 512;  // blocks (point chunks) of one weight-gradient reduction
 
 static void wgrad(pf_fno* F, const u16* A, int lda, int K, const float* D, int ldd, int N, float* gW, float* gb) {
   const long long per = (F->P + kWgradBlocks - 1) / kWgradBlocks;
@@ -599,7 +619,7 @@ static void wgrad(pf_fno* F, const u16* A, int lda, int K, const float* D, int l
   const int tiles = ((K + 31) / 32) * ((N + 31) / 32);
   for (int t0 = 0; t0 < tiles; t0 += 4) {
     k_wgrad_mfma<<<nb, 256, 0, F->stream>>>(A, lda, K, D, ldd, N, F->P, chunk, t0, F->part);
-    k_sum_partials<<<gdiv(KN, 256), 256, 0, F->stream>>>(F->part, 4 * nb, K, N, t0, gW, gb);
+    k_sum_partials<<<gdiv(KN, 64), 256, 0, F->stream>>>(F->part, nb, K, N, t0, gW, gb);
   }
 }
 
@@ -786,7 +806,7 @@ pf_status pf_fno_create(const pf_fno_config* cfg, void* stream, pf_fno** out) {
   A((void**)&F->dpreb, 2 * P * w);
   A((void**)&F->douthb, 2 * P * F->coutp);
   A((void**)&F->dSb, 2 * spec);
-  F->part_elems = 4LL * kWgradBlocks * (std::max(std::max(w, h), 8) + 1) * std::max(std::max(w, h), 8);
+  F->part_elems = (long long)kWgradBlocks * (std::max(std::max(w, h), 8) + 1) * std::max(std::max(w, h), 8);
   A((void**)&F->part, 4 * F->part_elems);
   A((void**)&F->dpart, 8 * (size_t)gdiv(P, 256));
   A((void**)&F->dsum, 8);
