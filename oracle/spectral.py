@@ -120,3 +120,15 @@ def brute_irdft3(U, shape):
     k = np.stack([kz.ravel(), ky.ravel(), kx.ravel()], axis=1).astype(float)
     phase = np.exp(2j * np.pi * (r @ k.T))
     return (phase @ full.ravel()).real.reshape(shape) / (nz * ny * nx)
+
+
+def dft_coefficient(u, m):
+    """One coefficient of the unnormalised forward transform by its definition,
+    X(m) = sum_r u(r) exp(-2 pi i (m_z z / N_z + m_y y / N_y + m_x x / N_x)),
+    summed axis by axis (x first), for a real field u[z][y][x] and an integer
+    mode m = (m_z, m_y, m_x).  O(N^3) per coefficient."""
+    nz, ny, nx = u.shape
+    ex = np.exp(-2j * np.pi * m[2] * np.arange(nx) / nx)
+    ey = np.exp(-2j * np.pi * m[1] * np.arange(ny) / ny)
+    ez = np.exp(-2j * np.pi * m[0] * np.arange(nz) / nz)
+    return complex(ez @ ((u @ ex) @ ey))

@@ -69,6 +69,33 @@ def test_fft3d_forward_inverse(torch, params, shape):
         assert _rel(back.cpu().numpy(), u) < 1e-13
 
 
+def test_fft3d_at_512_sampled_coefficients(torch, params):
+    """The 3D transform at the full 512^3 size (the bench's launch shapes, tuned
+    tile plans): sampled coefficients against the oracle's one-coefficient DFT
+    by definition, and the forward/inverse round trip over the whole field."""
+    _say("fft3d 512^3 sampled")
+    n = 512
+    rng = np.random.default_rng(21)
+    u = rng.standard_normal((1, n, n, n))
+    modes = [(0, 0, 0), (1, 0, 0), (0, 7, 3), (255, 1, 256), (300, 511, 17), (256, 256, 256), (5, 400, 100)]
+    want = [osp.dft_coefficient(u[0], m) for m in modes]
+    with _solver(n, params, method="imex_euler", dt0=0.05) as s:
+        s.set_state(u[0], np.zeros((3, n, n, n)))
+        s.autotune(1)
+        src = torch.from_numpy(u).cuda()
+        dst = s.kspace_empty(1)
+        s.fft3d(-1, 1, src, dst)
+        # rounding of a length-N^3 transform: ~eps log2(N^3) times the typical coefficient
+        rms = float(torch.linalg.vector_norm(dst[..., : n // 2 + 1])) / (n * n * (n // 2 + 1)) ** 0.5
+        for m, w in zip(modes, want):
+            got = complex(dst[0, m[0], m[1], m[2]].item())
+            assert abs(got - w) <= 1e-12 * 27 * rms, (m, got, w)
+        back = torch.empty_like(src)
+        s.fft3d(+1, 1, dst, back)
+        err = float(torch.linalg.vector_norm(back - src) / torch.linalg.vector_norm(src))
+        assert err < 1e-13, err
+
+
 def test_state_roundtrip(torch, params):
     _say("state roundtrip 32^3")
     _, c, eta = pfinputs.config("small32")
@@ -295,6 +322,61 @@ def test_mixed_precision_rhs_error_bound(torch, params, n):
     for f in range(4):
         assert _rel(gI[f], FI[f]) < TOL       # the implicit part stays FP64
         assert errs[f] < 1e-4
+
+
+def _band_limited_state(n):
+    """c and eta_1..3 built from cosines whose wavevector components are 0 or
+    +-1 (in units of 2 pi / L): every product the right-hand side forms (degree
+    <= 9 in the fields) stays below 9 per component, so on any grid with
+    N >= 20 the pointwise terms are exact and the spectrum is the same."""
+    i = np.arange(n) * (2 * np.pi / n)
+    z, y, x = np.meshgrid(i, i, i, indexing="ij")
+    c = 0.16 + 0.05 * np.cos(x + y + z) + 0.02 * np.sin(x - z)
+    eta = np.stack([0.45 + 0.2 * np.cos(x - y),
+                    0.3 + 0.1 * np.sin(y + z) + 0.05 * np.cos(x),
+                    0.2 + 0.15 * np.cos(z)])
+    return c, eta
+
+
+def test_rhs_at_512_matches_oracle_on_a_band_limited_state(torch, params):
+    """pf_rhs at the full 512^3 size, with the tile plans the autotuner picks,
+    against the oracle on 32^3 with dx scaled by 16 (the same physical box and
+    wavevectors): for a band-limited state the unnormalised spectra agree mode
+    for mode after division by N^3, and every mode the 32^3 grid cannot hold is
+    zero on the GPU."""
+    _say("rhs 512^3 band-limited")
+    big, small = 512, 32
+    p_small = dict(params)
+    p_small["dx"] = params.get("dx", 1.0) * big / small
+    c, eta = _band_limited_state(small)
+    m = om.Model((small,) * 3, p_small)
+    FI, FE = m.rhs(om.to_kspace(c, eta))
+    cb, eb = _band_limited_state(big)
+    with _solver(big, params, method="imex_euler", dt0=0.05) as s:
+        s.set_state(cb, eb)
+        s.autotune(1)
+        fI, fE = s.rhs(s.get_state_hat())
+        del cb, eb
+        # the modes the 32^3 grid holds: signed components in [-15, 16] (x: 0..16)
+        idx = np.concatenate([np.arange(0, small // 2 + 1), np.arange(big - small // 2 + 1, big)])
+        it = torch.from_numpy(idx).cuda()
+        for name, g, ref in (("fI", fI, FI), ("fE", fE, FE)):
+            sub = g.index_select(1, it).index_select(2, it)[..., : small // 2 + 1]
+            sub_np = sub.cpu().numpy() / float(big) ** 3
+            ref_n = ref / float(small) ** 3
+            for f in range(4):
+                rel = _rel(sub_np[f], ref_n[f])
+                assert rel < 1e-10, (name, f, rel)
+            # nothing outside the band
+            sel = torch.zeros(big, dtype=torch.bool, device="cuda")
+            sel[it] = True
+            band = sel[:, None, None] & sel[None, :, None] & \
+                (torch.arange(big // 2 + 1, device="cuda") < small // 2 + 1)[None, None, :]
+            outside = torch.where(band, torch.zeros((), dtype=g.dtype, device="cuda"), g[..., : big // 2 + 1])
+            rest = float(torch.linalg.vector_norm(outside))
+            tot = float(torch.linalg.vector_norm(sub))
+            del outside, band
+            assert rest <= 1e-10 * tot, (name, rest, tot)
 
 
 def test_mixed_precision_twin64_run_error_per_field(torch, params):

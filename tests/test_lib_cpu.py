@@ -43,6 +43,50 @@ def test_host_only_entry_points():
     assert L.pf_init(None, None, None) == -1
 
 
+def test_argument_checks_precede_any_device_work():
+    """Invalid parameters are rejected on the host, before the library touches
+    a device (so these run without a GPU)."""
+    from paper_2609_36100_amd import _lib
+    L = _lib.lib()
+    h = ctypes.c_void_p()
+
+    def init(**over):
+        p = _lib.make_params(32, None)
+        for k, v in over.items():
+            setattr(p, k, v)
+        return L.pf_init(ctypes.byref(p), None, ctypes.byref(h))
+
+    assert init(dx=0.0) == -1
+    assert init(M=-1.0) == -1
+    assert init(precision=7) == -1
+    assert init(method=5) == -1 and init(method=0) == -1
+    assert init(method=_lib.PF_IMEX_EULER, adaptive=1) == -1      # no embedding to control with
+    assert init(method=_lib.PF_ARK2, adaptive=1, atol=0.0) == -1
+    assert init(mean_strain_mode=2) == -1
+    assert init(nx=7) == -4 and init(nz=168) == -4
+    # ensembles: cubic supported sizes, one embedded method, one precision
+    arr = (_lib.Params * 2)()
+    arr[0] = _lib.make_params(32, None)
+    arr[1] = _lib.make_params(48, None)
+    assert L.pf_ensemble_init(0, arr, None, ctypes.byref(h)) == -1
+    arr[1] = _lib.make_params(256, None)
+    assert L.pf_ensemble_init(2, arr, None, ctypes.byref(h)) == -4
+    arr[1] = _lib.make_params(48, None, method="imex_euler")
+    assert L.pf_ensemble_init(2, arr, None, ctypes.byref(h)) == -1
+    arr[1] = _lib.make_params(48, None, method="ark324l")
+    assert L.pf_ensemble_init(2, arr, None, ctypes.byref(h)) == -1          # mixed methods
+    arr[1] = _lib.make_params(48, None, precision="mixed")
+    assert L.pf_ensemble_init(2, arr, None, ctypes.byref(h)) == -1
+    # the surrogate's shape limits
+    for bad in [(12, 32, 12, 4, 128, 4, 4), (128, 30, 12, 4, 128, 4, 4), (128, 32, 11, 4, 128, 4, 4),
+                (128, 32, 12, 4, 130, 4, 4), (16, 32, 12, 4, 128, 4, 4), (128, 32, 12, 0, 128, 4, 4)]:
+        cfg = _lib.FnoConfig(*bad)
+        assert L.pf_fno_create(ctypes.byref(cfg), None, ctypes.byref(h)) == -1, bad
+    d = ctypes.c_double()
+    assert L.pf_bandwidth_probe(1000, 5, None, ctypes.byref(d), ctypes.byref(d), ctypes.byref(d)) == -1
+    assert L.pf_rel_l2(None, None, 10, None, ctypes.byref(d)) == -1
+
+
 def test_params_struct_matches_header_layout():
     """sizeof of the ABI structs seen by ctypes equal the C compiler's."""
     from paper_2609_36100_amd import _lib

@@ -85,3 +85,12 @@ def test_wavevector_layout():
     assert np.isclose(ky[0, 5, 0], -2 * np.pi * 1 / 12)
     mult = sp.multiplicity((8, 6, 10))
     assert mult[0, 0, 0] == 1 and mult[0, 0, 5] == 1 and np.all(mult[0, 0, 1:5] == 2)
+
+
+def test_single_coefficient_by_definition_matches_brute_force():
+    rng = np.random.default_rng(11)
+    u = rng.standard_normal((6, 10, 12))
+    X = sp.brute_rdft3(u)
+    for m in [(0, 0, 0), (1, 2, 3), (5, 9, 6), (3, 0, 1)]:
+        want = X[m[0], m[1], m[2]]
+        assert abs(sp.dft_coefficient(u, m) - want) <= 1e-12 * np.abs(X).max()
