@@ -418,6 +418,47 @@ def orders_bench(torch, n, t_final):
     return out
 
 
+def oracle_timing(sizes_rhs=(64, 128, 256), sizes_step=(64, 128), threads=None):
+    """The FP64 CPU oracle as it stands, timed on this host: one explicit RHS
+    and one ARK4(3)6L step at several sizes, with NumPy's single-threaded FFT
+    and with SciPy's FFT on all cores (same seeded generator as the 512^3
+    workload, nucleus count scaled by volume)."""
+    import subprocess
+    import pfinputs
+    from oracle import ark as oark
+    from oracle import model as om
+    from oracle import spectral as osp
+    # the host share this process may use (the thread cap set for the job, at most the visible cores)
+    cores = threads or min(os.cpu_count() or 1, int(os.environ.get("OMP_NUM_THREADS", "16")))
+    try:
+        cpu = [l.split(":", 1)[1].strip() for l in subprocess.run(["lscpu"], capture_output=True, text=True)
+               .stdout.splitlines() if l.startswith("Model name")][0]
+    except Exception:
+        cpu = platform.processor() or platform.machine()
+    out = dict(cpu=cpu, cores=cores, rhs={}, ark4_step={})
+    for backend, workers in (("numpy", 1), ("scipy", cores)):
+        osp.set_fft_backend(backend, workers)
+        for n in sizes_rhs:
+            spec, c, eta = pfinputs.config("mixed512", n=n)
+            m = om.Model((n, n, n), pfinputs.default_params())
+            m.B()
+            y = om.to_kspace(c, eta)
+            t0 = time.perf_counter()
+            m.rhs(y)
+            wall = time.perf_counter() - t0
+            out["rhs"]["%s_%d" % (backend, n)] = dict(s=round(wall, 3), mpts_stages=round(n ** 3 / wall / 1e6, 3))
+            log("oracle rhs %s %d^3: %.2f s" % (backend, n, wall))
+            if n in sizes_step:
+                t0 = time.perf_counter()
+                _, _, ne = oark.ark_step(y, 0.1, oark.ark436l2sa(), m.f_explicit, m.implicit_symbol())
+                wall = time.perf_counter() - t0
+                out["ark4_step"]["%s_%d" % (backend, n)] = dict(s=round(wall, 3),
+                                                                mpts_stages=round(n ** 3 * ne / wall / 1e6, 3))
+                log("oracle ark4 step %s %d^3: %.2f s" % (backend, n, wall))
+    osp.set_fft_backend("numpy", 1)
+    return out
+
+
 def fno_step_bench(torch, n=128, reps=10):
     """The surrogate's kernels on their own: one training step (forward, loss,
     backward) and one surrogate advance at n^3 (width 32, 12 modes, 4 layers),
@@ -473,8 +514,8 @@ def main():
     ap.add_argument("--skip-mixed", action="store_true")
     ap.add_argument("--skip-fft", action="store_true")
     ap.add_argument("--skip-cpu", action="store_true")
-    ap.add_argument("--mode", choices=["throughput", "ensemble", "time_to_t", "fno", "fno_step", "orders"],
-                    default="throughput")
+    ap.add_argument("--mode", choices=["throughput", "ensemble", "time_to_t", "fno", "fno_step", "orders",
+                                       "oracle_timing"], default="throughput")
     ap.add_argument("--runs", type=int, default=40, help="fno: training runs")
     ap.add_argument("--val-runs", type=int, default=4, help="fno: held-out runs")
     ap.add_argument("--snapshots", type=int, default=50, help="fno: snapshots per run")
@@ -530,6 +571,13 @@ def main():
                                                  "uneven ensemble's 128^3 members, to t=%g, checks every 5th "
                                                  "advance at rel-L2(c) 1e-3" % g["t_final"]},
                           "fno": r}), flush=True)
+        return
+    if args.mode == "oracle_timing":
+        r = oracle_timing()
+        print(json.dumps({"metric": METRIC, "mode": "oracle_timing", "unit": "Mpts·stages/s", "value": None,
+                          "higher_is_better": True, "n_gpus": 0, "dtype": "f64", "data": "synthetic",
+                          "config": {"workload": "FP64 CPU oracle: one RHS and one ARK4 step at several sizes"},
+                          "oracle_timing": r}), flush=True)
         return
     if args.mode == "fno_step":
         r = fno_step_bench(torch, args.n if args.n != 512 else 128)

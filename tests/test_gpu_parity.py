@@ -342,15 +342,20 @@ def test_rhs_at_512_matches_oracle_on_a_band_limited_state(torch, params):
     """pf_rhs at the full 512^3 size, with the tile plans the autotuner picks,
     against the oracle on 32^3 with dx scaled by 16 (the same physical box and
     wavevectors): for a band-limited state the unnormalised spectra agree mode
-    for mode after division by N^3, and every mode the 32^3 grid cannot hold is
-    zero on the GPU."""
+    for mode after division by N^3, and the modes the 32^3 grid cannot hold
+    are round-off on the GPU: 1e-12 of the state (the transform's rounding),
+    1e-8 of the explicit derivative (high-k round-off is amplified by k^2 up
+    to ~30 in the composition's term; leakage or aliasing would be O(1)).
+    The implicit derivative is L(k) times the state mode by mode, so the
+    state's check covers it outside the band."""
     _say("rhs 512^3 band-limited")
     big, small = 512, 32
     p_small = dict(params)
     p_small["dx"] = params.get("dx", 1.0) * big / small
     c, eta = _band_limited_state(small)
     m = om.Model((small,) * 3, p_small)
-    FI, FE = m.rhs(om.to_kspace(c, eta))
+    Y = om.to_kspace(c, eta)
+    FI, FE = m.rhs(Y)
     cb, eb = _band_limited_state(big)
     with _solver(big, params, method="imex_euler", dt0=0.05) as s:
         s.set_state(cb, eb)
@@ -360,13 +365,17 @@ def test_rhs_at_512_matches_oracle_on_a_band_limited_state(torch, params):
         # the modes the 32^3 grid holds: signed components in [-15, 16] (x: 0..16)
         idx = np.concatenate([np.arange(0, small // 2 + 1), np.arange(big - small // 2 + 1, big)])
         it = torch.from_numpy(idx).cuda()
-        for name, g, ref in (("fI", fI, FI), ("fE", fE, FE)):
+        y_hat = s.get_state_hat()
+        for name, g, ref, out_tol in (("y", y_hat, Y, 1e-12), ("fI", fI, FI, None), ("fE", fE, FE, 1e-8)):
             sub = g.index_select(1, it).index_select(2, it)[..., : small // 2 + 1]
-            sub_np = sub.cpu().numpy() / float(big) ** 3
-            ref_n = ref / float(small) ** 3
-            for f in range(4):
-                rel = _rel(sub_np[f], ref_n[f])
-                assert rel < 1e-10, (name, f, rel)
+            if ref is not None:
+                sub_np = sub.cpu().numpy() / float(big) ** 3
+                ref_n = ref / float(small) ** 3
+                for f in range(4):
+                    rel = _rel(sub_np[f], ref_n[f])
+                    assert rel < 1e-10, (name, f, rel)
+            if out_tol is None:
+                continue
             # nothing outside the band
             sel = torch.zeros(big, dtype=torch.bool, device="cuda")
             sel[it] = True
@@ -376,7 +385,7 @@ def test_rhs_at_512_matches_oracle_on_a_band_limited_state(torch, params):
             rest = float(torch.linalg.vector_norm(outside))
             tot = float(torch.linalg.vector_norm(sub))
             del outside, band
-            assert rest <= 1e-10 * tot, (name, rest, tot)
+            assert rest <= out_tol * tot, (name, rest, tot)
 
 
 def test_mixed_precision_twin64_run_error_per_field(torch, params):
