@@ -211,16 +211,17 @@ def ensemble_bench(torch, count, t_final, rtol, atol, ref_members, precisions=("
     return out
 
 
-def time_to_t_bench(torch, n, t_final, rtol, atol, precisions=("fp64", "mixed")):
-    """Adaptive ARK4 run of the seeded n^3 workload to t_final; vf error against rtol 1e-8."""
+def time_to_t_bench(torch, n, t_final, rtol, atol, precisions=("fp64", "mixed"), workload="adaptive256"):
+    """Adaptive ARK4 run of a seeded n^3 workload to t_final; volume-fraction and
+    per-field state errors against an rtol 1e-8 plain FP64 reference."""
     import pfinputs
-    from paper_2609_36100_amd import Solver
-    spec, c, eta = pfinputs.config("adaptive256", n=n)
-    out = dict(n=n, t_final=t_final, rtol=rtol, atol=atol, nuclei=spec["n_nuclei"])
-    vf = {}
+    from paper_2609_36100_amd import Solver, rel_l2
+    spec, c, eta = pfinputs.config(workload, n=n)
+    out = dict(n=n, workload=workload, t_final=t_final, rtol=rtol, atol=atol, nuclei=spec["n_nuclei"])
+    vf, states = {}, {}
     for prec in precisions:
         log("time-to-t %s" % prec)
-        with Solver(n, None, method="ark436l", precision=prec, adaptive=True, dt0=0.1, rtol=rtol, atol=atol) as s:
+        with Solver(n, None, method="ark436l", precision=prec, adaptive=True, dt0=0.01, rtol=rtol, atol=atol) as s:
             s.set_state(c, eta)
             s.autotune(2)
             torch.cuda.synchronize()
@@ -229,134 +230,20 @@ def time_to_t_bench(torch, n, t_final, rtol, atol, precisions=("fp64", "mixed"))
             torch.cuda.synchronize()
             wall = time.perf_counter() - t0
             vf[prec] = s.diagnostics()["vf"]
+            states[prec] = s.get_state_device().clone()
         out[prec] = dict(wall_s=round(wall, 3), steps=st["steps"], rejects=st["rejects"],
                          value=round(n ** 3 * st["n_rhs"] / wall / 1e6, 1), vf=vf[prec])
+        log("time-to-t %s: %.2f s, %d steps" % (prec, wall, st["steps"]))
     log("time-to-t reference (rtol 1e-8)")
-    with Solver(n, None, method="ark436l", adaptive=True, dt0=0.05, rtol=1e-8, atol=1e-11) as s:
+    with Solver(n, None, method="ark436l", adaptive=True, dt0=0.01, rtol=1e-8, atol=1e-11) as s:
         s.set_state(c, eta)
         s.advance(t_final)
         ref = s.diagnostics()["vf"]
+        uref = s.get_state_device()
+        for prec in precisions:
+            out[prec]["vf_error"] = float("%.3e" % abs(vf[prec] - ref))
+            out[prec]["state_rel_l2"] = [float("%.3e" % rel_l2(states[prec][f], uref[f])) for f in range(4)]
     out["vf_ref"] = ref
-    for prec in precisions:
-        out[prec]["vf_error"] = float("%.3e" % abs(vf[prec] - ref))
-    return out
-
-
-def fno_bench(torch, t_final, runs, val_runs, snapshots, epochs, train_s, members, dt_ref_t, lr, ensemble=True):
-    """Learned surrogate: plain-solver training data at 128^3, GPU training, held-out
-    validation, then the 128^3 members of the uneven ensemble advanced to t_final
-    with the checked surrogate against plain adaptive ARK4 (the gain test)."""
-    import numpy as np
-    import pfinputs
-    from paper_2609_36100_amd import Solver, rel_l2
-    from paper_2609_36100_amd import surrogate as sg
-    n = 128
-    out = dict(n=n, width=32, modes=12, layers=4, hidden=128)
-    t0 = time.perf_counter()
-    dt_ref, _ = sg.reference_dt(n, 0, dt_ref_t)
-    delta = 10.0 * dt_ref
-    out.update(dt_ref=dt_ref, delta=delta, dt_ref_window=dt_ref_t)
-    log("dt_ref %.5f (mean accepted ARK4 step over [0, %g] of run 0), delta %.5f" % (dt_ref, dt_ref_t, delta))
-    snaps, steps = sg.generate_snapshots(n, runs + val_runs, snapshots, delta, log=log)
-    out["data"] = dict(runs=runs, val_runs=val_runs, snapshots=snapshots, pairs=runs * snapshots,
-                       plain_steps=steps, wall_s=round(time.perf_counter() - t0, 1))
-    scale = sg.increment_scale(snaps, runs)
-    norm = sg.state_norm(snaps, runs)
-    out["scale"] = [float("%.4e" % v) for v in scale]
-    out["input_norm"] = dict(mean=[float("%.4e" % v) for v in norm[0]], std=[float("%.4e" % v) for v in norm[1]])
-    f = sg.make_fno(n, 32, 12, 4, 128, seed=0, scale=scale, norm=norm)
-    val = list(range(runs, runs + val_runs))
-    e0, keep, inc0 = sg.validate(f, snaps, val)
-    t1 = time.perf_counter()
-    hist = sg.train(f, snaps, runs, epochs=epochs, lr=lr, batch=4, seed=0, log=log, time_limit=train_s)
-    out["train"] = dict(epochs=len(hist), loss=[float("%.4e" % v) for v in hist],
-                        wall_s=round(time.perf_counter() - t1, 1))
-    e1, _, inc1 = sg.validate(f, snaps, val)
-    out["validation_rel_l2_c"] = dict(untrained_mean=float("%.3e" % e0.mean()), trained_mean=float("%.3e" % e1.mean()),
-                                      trained_max=float("%.3e" % e1.max()), no_change_mean=float("%.3e" % keep.mean()),
-                                      frac_below_tol=float("%.3f" % (e1 <= 1e-3).mean()),
-                                      increment_rel_err=[float("%.3f" % v) for v in inc1],
-                                      increment_rel_err_untrained=[float("%.3f" % v) for v in inc0])
-    log("validation rel-L2(c): trained %.3e (max %.3e), untrained %.3e, no change %.3e"
-        % (e1.mean(), e1.max(), e0.mean(), keep.mean()))
-    del snaps
-    torch.cuda.empty_cache()
-    # gain test on the ensemble's 128^3 members
-    mem = [m for m in pfinputs.ensemble_members(64) if m["n"] == n][:members]
-    # default horizon: the training window (snapshots x delta)
-    n_adv = int(round(t_final / delta)) if t_final > 0 else snapshots
-    t_end = n_adv * delta
-    kw = dict(method="ark436l", adaptive=True, dt0=0.01, rtol=1e-6, atol=1e-9)
-    res = []
-    tot_plain = tot_sur = 0.0
-    for i, m in enumerate(mem):
-        with Solver(n, None, **kw) as s:
-            s.set_state(m["c"], m["eta"])
-            torch.cuda.synchronize()
-            ta = time.perf_counter()
-            st = s.advance(t_end)
-            torch.cuda.synchronize()
-            w_plain = time.perf_counter() - ta
-            u_plain = s.get_state_device().clone()
-            vf_plain = s.diagnostics()["vf"]
-            s.set_state(m["c"], m["eta"])
-            u = s.get_state_device().clone()
-            s.set_dt(0.01)
-            torch.cuda.synchronize()
-            ta = time.perf_counter()
-            fs = sg.checked_advance(f, s, u, t_end, delta, check_every=5, tol=1e-3)
-            torch.cuda.synchronize()
-            w_sur = time.perf_counter() - ta
-            s.set_state_device(u)
-            vf_sur = s.diagnostics()["vf"]
-        with Solver(n, None, method="ark436l", adaptive=True, dt0=0.01, rtol=1e-8, atol=1e-11) as r:
-            r.set_state(m["c"], m["eta"])
-            r.advance(t_end)
-            u_ref = r.get_state_device()
-            vf_ref = r.diagnostics()["vf"]
-        tot_plain += w_plain
-        tot_sur += w_sur
-        d = fs.as_dict()
-        res.append(dict(member=m["member"], plain_s=round(w_plain, 3), plain_steps=st["steps"],
-                        surrogate_s=round(w_sur, 3), surrogate=d["surrogate"], checks=d["checks"],
-                        fallbacks=d["fallbacks"], plain_advances=d["plain"],
-                        check_err_max=float("%.3e" % d["err_max"]),
-                        vf_err_plain=float("%.3e" % abs(vf_plain - vf_ref)),
-                        vf_err_surrogate=float("%.3e" % abs(vf_sur - vf_ref)),
-                        c_rel_l2_plain=float("%.3e" % rel_l2(u_plain[0], u_ref[0])),
-                        c_rel_l2_surrogate=float("%.3e" % rel_l2(u[0], u_ref[0]))))
-        log("member %d: plain %.2f s (%d steps), surrogate %.2f s (%d net, %d checks, %d fallbacks), "
-            "vf err %.1e / %.1e" % (m["member"], w_plain, st["steps"], w_sur, d["surrogate"], d["checks"],
-                                    d["fallbacks"], res[-1]["vf_err_plain"], res[-1]["vf_err_surrogate"]))
-    out["gain"] = dict(t_final=t_end, members=len(mem), plain_s=round(tot_plain, 3), surrogate_s=round(tot_sur, 3),
-                       speedup=round(tot_plain / tot_sur, 3) if tot_sur > 0 else None,
-                       vf_err_max_plain=max(r["vf_err_plain"] for r in res),
-                       vf_err_max_surrogate=max(r["vf_err_surrogate"] for r in res),
-                       fallbacks=sum(r["fallbacks"] for r in res), per_member=res)
-    if ensemble:
-        # the whole uneven ensemble: batched plain solver for every member, against batched
-        # plain for the other sizes plus the checked surrogate for the 128^3 members
-        from paper_2609_36100_amd import Ensemble
-        allm = pfinputs.ensemble_members(64)
-        rest = [m for m in allm if m["n"] != n]
-        walls = {}
-        for name, group in (("all_plain", allm), ("other_sizes_plain", rest)):
-            log("ensemble %s (%d members) to t=%g" % (name, len(group), t_end))
-            with Ensemble([dict(n=m["n"], **kw) for m in group]) as E:
-                for i, m in enumerate(group):
-                    E.set_state(i, m["c"], m["eta"])
-                torch.cuda.synchronize()
-                ta = time.perf_counter()
-                E.advance(t_end)
-                torch.cuda.synchronize()
-                walls[name] = time.perf_counter() - ta
-        full128 = sum(1 for m in allm if m["n"] == n)
-        sur_all = tot_sur * full128 / max(len(mem), 1)
-        out["gain"]["ensemble"] = dict(
-            members=len(allm), members_128=full128, all_plain_s=round(walls["all_plain"], 3),
-            other_sizes_plain_s=round(walls["other_sizes_plain"], 3),
-            with_surrogate_s=round(walls["other_sizes_plain"] + sur_all, 3),
-            speedup=round(walls["all_plain"] / (walls["other_sizes_plain"] + sur_all), 3))
     return out
 
 
@@ -525,6 +412,9 @@ def main():
     ap.add_argument("--dt-ref-window", type=float, default=10.0, help="fno: window for the mean ARK4 step")
     ap.add_argument("--lr", type=float, default=1e-3, help="fno: peak learning rate")
     ap.add_argument("--skip-ensemble", action="store_true", help="fno: skip the whole-ensemble comparison")
+    ap.add_argument("--workload", default="adaptive256", choices=["adaptive256", "mixed512"],
+                    help="time_to_t: seeded initial condition")
+    ap.add_argument("--rtol", type=float, default=1e-6, help="time_to_t: relative tolerance (atol = rtol / 1000)")
     ap.add_argument("--t-final", type=float, default=None)
     ap.add_argument("--members", type=int, default=64)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -598,12 +488,12 @@ def main():
                           "orders": r}), flush=True)
         return
     if args.mode == "time_to_t":
-        n = args.n if args.n != 512 else 256
-        r = time_to_t_bench(torch, n, args.t_final or 500.0, 1e-6, 1e-9)
+        n = args.n if (args.n != 512 or args.workload != "adaptive256") else 256
+        r = time_to_t_bench(torch, n, args.t_final or 500.0, args.rtol, args.rtol * 1e-3, workload=args.workload)
         print(json.dumps({"metric": METRIC, "mode": "time_to_t", "unit": "s", "value": r["fp64"]["wall_s"],
                           "higher_is_better": False, "n_gpus": 1, "dtype": "f64", "data": "synthetic",
-                          "config": {"workload": "%d^3, %d seeded nuclei, adaptive ARK4(3)6L rtol 1e-6 to t=%g"
-                                                 % (n, r["nuclei"], r["t_final"])},
+                          "config": {"workload": "%d^3 (%s), %d seeded nuclei, adaptive ARK4(3)6L rtol %g to t=%g"
+                                                 % (n, args.workload, r["nuclei"], args.rtol, r["t_final"])},
                           "time_to_t": r}), flush=True)
         return
     n = args.n

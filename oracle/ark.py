@@ -14,7 +14,7 @@ a + b sqrt 2; ARK3(2)4L[2]SA and ARK4(3)6L[2]SA of Kennedy & Carpenter (2003,
 Appl. Numer. Math. 44), the third- and fourth-order methods the paper's
 order study cites; their coefficients are the published rationals.
 
-Readings (listed in the design doc): the WRMS vector is the reciprocal-space state
+Readings (where the paper leaves a choice): the WRMS vector is the reciprocal-space state
 scaled to unit norm (Parseval), modes weighted by their half-spectrum
 multiplicity; the step-size controller, which the paper leaves to the
 library, is the elementary I-controller ``dt * min(5, max(0.2, 0.9 err^(-1/(q+1))))``

@@ -16,7 +16,7 @@ dimensionless stand-in model with one homogeneous stiffness tensor):
   (Eq. phi_gov), written in reciprocal space and split into a stiff linear
   implicit part and a nonlinear explicit part (Eqs. composition, order).
 
-Readings of the paper used here (each listed in the design doc):
+Readings of the paper used here (where it is silent or garbled):
 * implicit CH symbol ``-M k^2 (a_c + kappa_c k^2)`` with ``a_c = 2W`` (split
   B, default) or 0 (split A); implicit AC symbol ``-L kappa_eta k^2``;
 * mean strain either prescribed (``eps_bar``, default 0) or stress-free.

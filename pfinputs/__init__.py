@@ -135,7 +135,7 @@ def single_mode(n, m=(1, 0, 0), amp=1e-3, c0=0.16, phase=0.0):
 
 
 # Named synthetic workloads -------------------------------------------------
-_CONFIGS = {
+_WORKLOADS = {
     # 32^3 IMEX Euler, dt 0.05, 200 steps; 4 nuclei radius 3
     "small32": dict(n=32, seed=1000, c0=0.16, n_nuclei=4, radius=3, d_min=8.0,
                     method="imex_euler", dt=0.05, steps=200),
@@ -157,7 +157,7 @@ def config(name, n=None):
 
     Overriding ``n`` scales the nucleus count by volume (at least 1).
     """
-    spec = dict(_CONFIGS[name])
+    spec = dict(_WORKLOADS[name])
     if n is not None and n != spec["n"]:
         scale = (n / spec["n"]) ** 3
         spec["n_nuclei"] = max(1, int(round(spec["n_nuclei"] * scale)))
