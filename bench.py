@@ -237,7 +237,9 @@ def time_to_t_bench(torch, n, t_final, rtol, atol, precisions=("fp64", "mixed"),
     log("time-to-t reference (rtol 1e-8)")
     with Solver(n, None, method="ark436l", adaptive=True, dt0=0.01, rtol=1e-8, atol=1e-11) as s:
         s.set_state(c, eta)
-        s.advance(t_final)
+        for k in range(1, 21):   # in twentieths, with a progress line each
+            st = s.advance(t_final * k / 20)
+            log("reference: t = %g, %d steps" % (st["t"], st["steps"]))
         ref = s.diagnostics()["vf"]
         uref = s.get_state_device()
         for prec in precisions:

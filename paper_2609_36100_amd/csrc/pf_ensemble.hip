@@ -609,6 +609,8 @@ pf_status pf_ensemble_init(int32_t n, const pf_params* per_member, void* stream,
     if (p.precision != PF_FP64 && p.precision != PF_MIXED) return PF_ERR_ARG;
     if (p.dx <= 0.0 || (p.adaptive && (p.rtol < 0.0 || p.atol <= 0.0))) return PF_ERR_ARG;
   }
+  int ndev = 0;  // no usable device: a HIP error, before any allocation
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return PF_ERR_HIP;
   pf_ens* E = new (std::nothrow) pf_ens();
   if (!E) return PF_ERR_OOM;
   E->M = n;

@@ -727,6 +727,8 @@ pf_status pf_fno_create(const pf_fno_config* cfg, void* stream, pf_fno** out) {
       c.modes % 2 || 2 * c.modes > c.n || c.layers < 1 || c.layers > 8 || c.hidden < 8 || c.hidden > 128 || c.hidden % 8 ||
       c.cin < 1 || c.cin > 8 || c.cout < 1 || c.cout > 8)
     return PF_ERR_ARG;
+  int ndev = 0;  // no usable device: a HIP error, before any allocation
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return PF_ERR_HIP;
   pf_fno* F = new (std::nothrow) pf_fno();
   if (!F) return PF_ERR_OOM;
   F->cfg = c;

@@ -704,6 +704,8 @@ pf_status pf_init(const pf_params* p, void* stream, pf_ctx** out) {
   if (!pf_size_supported(p->nx) || !pf_size_supported(p->ny) || !pf_size_supported(p->nz))
     return PF_ERR_UNSUPPORTED_SIZE;
 
+  int ndev = 0;  // no usable device: a HIP error, before any allocation
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return PF_ERR_HIP;
   pf_ctx* c = new (std::nothrow) pf_ctx();
   if (!c) return PF_ERR_OOM;
   ctx_setup(c, p, (hipStream_t)stream);

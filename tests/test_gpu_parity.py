@@ -300,10 +300,12 @@ def test_ark2_ark3_adaptive_replay_and_decisions(torch, params, method):
             assert _rel(g, yref) < TOL
 
 
+@pytest.mark.parametrize("variant", [0, 1])
 @pytest.mark.parametrize("n", [32, 64])
-def test_mixed_precision_rhs_error_bound(torch, params, n):
-    """FP32 FFT / pointwise / elastic work against the FP64 oracle: stated bound 1e-4 per field."""
-    _say("mixed rhs", n)
+def test_mixed_precision_rhs_error_bound(torch, params, n, variant):
+    """FP32 FFT / pointwise / elastic work against the FP64 oracle: stated bound
+    1e-4 per field, for both tile variants of every column pass."""
+    _say("mixed rhs", n, "variant", variant)
     spec, c, eta = pfinputs.config("twin64", n=n)
     m = om.Model((n, n, n), params)
     y = om.to_kspace(c, eta)
@@ -313,6 +315,8 @@ def test_mixed_precision_rhs_error_bound(torch, params, n):
         y, _, _ = oark.ark_step(y, 0.05, oark.imex_euler(), m.f_explicit, m.implicit_symbol())
     FI, FE = m.rhs(y)
     with _solver(n, params, precision="mixed") as s:
+        for k in range(4):
+            s.set_tuning(k, variant)
         fI, fE = s.rhs(s.kspace_from_numpy(y))
         gI, gE = s.kspace_to_numpy(fI), s.kspace_to_numpy(fE)
     # a variant with no nucleus has eta = 0 exactly and F^E = 0 on both sides

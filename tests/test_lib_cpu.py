@@ -117,3 +117,23 @@ def test_fft_building_blocks_on_host():
     assert len(lines) >= 60
     for name, n, err in lines:
         assert float(err) < 1e-14, (name, n, err)
+
+
+def test_plain_c_client_builds_and_reports_missing_device():
+    """include/pf.h is plain C: a C99 client compiles and links against libpf.so;
+    on a machine without a GPU its pf_init fails with PF_ERR_HIP, not a crash."""
+    exe = "/tmp/pf_abi_c_client"
+    r = subprocess.run(["gcc", "-std=c99", "-Wall", "-Werror", "-O1", "-I", os.path.join(ROOT, "include"), "-o", exe,
+                        os.path.join(ROOT, "tests", "native", "abi_c_client.c"),
+                        "-L", os.path.join(ROOT, "paper_2609_36100_amd"), "-lpf",
+                        "-Wl,-rpath," + os.path.join(ROOT, "paper_2609_36100_amd")],
+                       capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr[-2000:]
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a device is present: the GPU test runs this client")
+    import numpy as np
+    np.zeros(4 * 8 ** 3).tofile("/tmp/pf_abi_in.bin")
+    out = subprocess.run([exe, "8", "/tmp/pf_abi_in.bin", "/tmp/pf_abi_out.bin"], capture_output=True, text=True,
+                         timeout=120)
+    assert out.returncode == 10 and "PF_ERR_HIP" in out.stderr, (out.returncode, out.stderr)
