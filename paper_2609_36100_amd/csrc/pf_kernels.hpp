@@ -55,9 +55,12 @@ __device__ inline double lsym(const ModelK& m, int f, double k2) {
   return f == 0 ? -m.M * k2 * (m.ac + m.kc * k2) : -m.L * m.ke * k2;
 }
 
-// Khachaturyan kernel contraction e_v = sum_w B_vw(k) th_w for k != 0:
-// B_vw = E_vw - (S_v k) . Omega(k) . (S_w k),  Omega(k)^-1 = C_ijkl k_j k_l.
-// Uses k directly (Omega scales as 1/|k|^2, S k as |k|): no normalisation.
+// Khachaturyan kernel contraction e_v = sum_w B_vw(k) th_w for k != 0, with
+// B_vw = E_vw - (S_v k) . Omega(k) . (S_w k),  Omega(k)^-1 = C_ijkl k_j k_l
+// (S_v k componentwise).  Evaluated without forming B: q = sum_w (S_w k) th_w,
+// p = Omega q (adjugate over determinant, Omega symmetric), then
+// e_v = sum_w E_vw th_w - (S_v k) . p.  Uses k directly (Omega scales as
+// 1/|k|^2, S k as |k|): no normalisation.
 template <typename R>
 __device__ inline void elastic_apply(const ModelK& m, R kx, R ky, R kz, const cx<R>* th, cx<R>* e) {
   const R C11 = (R)m.C11, C12 = (R)m.C12, C44 = (R)m.C44;
@@ -76,29 +79,23 @@ __device__ inline void elastic_apply(const ModelK& m, R kx, R ky, R kz, const cx
   const R A01 = g02 * g12 - g01 * g22;
   const R A02 = g01 * g12 - g02 * g11;
   const R A12 = g01 * g02 - g00 * g12;
-  const R det = g00 * A00 + g01 * A01 + g02 * A02;
-  const R idet = (R)1 / det;
-  R s[3][3];  // s_v = S_v k  (componentwise)
-  R u[3][3];  // u_v = adj * s_v
+  const R idet = (R)1 / (g00 * A00 + g01 * A01 + g02 * A02);
+  cx<R> q0 = mk<R>(0, 0), q1 = mk<R>(0, 0), q2 = mk<R>(0, 0);
 #pragma unroll
-  for (int v = 0; v < 3; ++v) {
-    s[v][0] = (R)m.S[v][0] * kx;
-    s[v][1] = (R)m.S[v][1] * ky;
-    s[v][2] = (R)m.S[v][2] * kz;
-    u[v][0] = A00 * s[v][0] + A01 * s[v][1] + A02 * s[v][2];
-    u[v][1] = A01 * s[v][0] + A11 * s[v][1] + A12 * s[v][2];
-    u[v][2] = A02 * s[v][0] + A12 * s[v][1] + A22 * s[v][2];
+  for (int w = 0; w < 3; ++w) {
+    q0 = q0 + ((R)m.S[w][0] * kx) * th[w];
+    q1 = q1 + ((R)m.S[w][1] * ky) * th[w];
+    q2 = q2 + ((R)m.S[w][2] * kz) * th[w];
   }
+  const cx<R> p0 = idet * (A00 * q0 + A01 * q1 + A02 * q2);
+  const cx<R> p1 = idet * (A01 * q0 + A11 * q1 + A12 * q2);
+  const cx<R> p2 = idet * (A02 * q0 + A12 * q1 + A22 * q2);
 #pragma unroll
   for (int v = 0; v < 3; ++v) {
     cx<R> acc = mk<R>(0, 0);
 #pragma unroll
-    for (int w = 0; w < 3; ++w) {
-      const R q = (s[w][0] * u[v][0] + s[w][1] * u[v][1] + s[w][2] * u[v][2]) * idet;
-      const R bvw = (R)m.E[v][w] - q;
-      acc = acc + bvw * th[w];
-    }
-    e[v] = acc;
+    for (int w = 0; w < 3; ++w) acc = acc + (R)m.E[v][w] * th[w];
+    e[v] = acc - (((R)m.S[v][0] * kx) * p0 + ((R)m.S[v][1] * ky) * p1 + ((R)m.S[v][2] * kz) * p2);
   }
 }
 
@@ -234,6 +231,20 @@ __device__ inline int xcd_tile(int b, int nb) {
 
 template <typename T>
 __device__ inline cx<T> ld(const cx<T>* p) { return *p; }
+
+// Element i of an array at f, addressed as a uniform base plus a 32-bit byte
+// offset: one field of the largest supported grid (512^3, row pitch 264) is
+// 1.1 GB, so in-field offsets fit, and the compiler then keeps one VGPR per
+// offset (shared by every field read at that position) instead of a 64-bit
+// address per access.
+template <typename E>
+__device__ inline E& at32(E* f, uint32_t i) {
+  return *reinterpret_cast<E*>(reinterpret_cast<char*>(f) + i * (uint32_t)sizeof(E));
+}
+template <typename E>
+__device__ inline const E& at32(const E* f, uint32_t i) {
+  return *reinterpret_cast<const E*>(reinterpret_cast<const char*>(f) + i * (uint32_t)sizeof(E));
+}
 
 template <typename T>
 __device__ inline cx<T> to_t(cx<double> z) { return mk<T>((T)z.re, (T)z.im); }
@@ -562,7 +573,7 @@ k_colfft_ws(const cx<T>* in, cx<T>* out, Geo g, int nf, const cx<T>* tw, T scale
 }
 
 // ---- K-E: forward z-FFT of theta, elastic solve, explicit CH, inverse z ----
-template <typename T, typename TE, int N, int TX, int RE, bool GUARD = false>
+template <typename T, typename TE, int N, int TX, int RE, bool GUARD = false, bool LB = false>
 __device__ inline void body_zpass_elastic(cx<T>* th, const Geo& g, const ModelK& m, const cx<T>* twz, cx<TE>* FEc,
                                           int accumulate, int tile, int tid, cx<T>* lds) {
   using CG = ColGeo<N, TX, RE>;
@@ -574,27 +585,24 @@ __device__ inline void body_zpass_elastic(cx<T>* th, const Geo& g, const ModelK&
   const int bf = tid / TX;
   const int x = xb * TX + col;
   const bool valid = act && x < g.nxh;
-  const long long lstride = (long long)g.ny * g.P;
-  const long long base = (long long)y * g.P + x;
+  const uint32_t lstride = (uint32_t)(g.ny * g.P);
+  const uint32_t base = (uint32_t)(y * g.P + x);
   auto buf = [&](int pos) -> cx<T>& { return lds[pos * CG::LD + col]; };
   cx<T> a[3][CG::R0];
-  // FP32: all three fields are loaded before the first transform, so their
-  // HBM latency is paid once (measured 4.6% faster at 512^3); FP64: field by
-  // field (3% faster: the early loads lengthen the first transform there)
-  constexpr bool hoist = sizeof(T) == 4;
+  // All three fields are loaded before the first transform.  With LB the
+  // transforms synchronise with LDS-only barriers (twz then points to LDS), so
+  // the loads of fields 1 and 2 stay in flight while field 0 is transformed,
+  // and the stores of the inverse transforms overlap the next one.
 #pragma unroll
   for (int v = 0; v < 3; ++v) {
 #pragma unroll
     for (int t = 0; t < CG::R0; ++t) {
       const int z = bf + t * CG::TL;
-      a[v][t] = valid ? th[v * g.fs + base + z * lstride] : mk<T>(0, 0);
+      a[v][t] = valid ? at32(th + v * g.fs, base + z * lstride) : mk<T>(0, 0);
     }
-    if constexpr (!hoist) line_fft<T, N, -1, RE>(a[v], bf, twz, buf, act);
   }
-  if constexpr (hoist) {
 #pragma unroll
-    for (int v = 0; v < 3; ++v) line_fft<T, N, -1, RE>(a[v], bf, twz, buf, act);
-  }
+  for (int v = 0; v < 3; ++v) line_fft<T, N, -1, RE, LB>(a[v], bf, twz, buf, act);
   const T kx = (T)(x * g.kfx);
   const T ky = (T)(mode_of(y, g.ny) * g.kfy);
 #pragma unroll
@@ -619,12 +627,12 @@ __device__ inline void body_zpass_elastic(cx<T>* th, const Geo& g, const ModelK&
       const T k2 = kx * kx + ky * ky + kz * kz;
       cx<T> Hs = thv[0] + thv[1] + thv[2];
       cx<T> fe = ((T)m.fEc * k2) * Hs;
-      const long long idx = base + z * lstride;
+      const uint32_t idx = base + z * lstride;
       if (accumulate) {
-        cx<TE> old = FEc[idx];
-        FEc[idx] = mk<TE>((TE)(old.re + fe.re), (TE)(old.im + fe.im));
+        cx<TE> old = at32(FEc, idx);
+        at32(FEc, idx) = mk<TE>((TE)(old.re + fe.re), (TE)(old.im + fe.im));
       } else {
-        FEc[idx] = mk<TE>((TE)fe.re, (TE)fe.im);
+        at32(FEc, idx) = mk<TE>((TE)fe.re, (TE)fe.im);
       }
     }
     const T s = (T)m.inv_n3;
@@ -635,12 +643,12 @@ __device__ inline void body_zpass_elastic(cx<T>* th, const Geo& g, const ModelK&
   }
 #pragma unroll
   for (int v = 0; v < 3; ++v) {
-    line_fft<T, N, +1, RE>(a[v], bf, twz, buf, act);
+    line_fft<T, N, +1, RE, LB>(a[v], bf, twz, buf, act);
     if (valid) {
 #pragma unroll
       for (int t = 0; t < CG::R0; ++t) {
         const int z = bf + t * CG::TL;
-        th[v * g.fs + base + z * lstride] = a[v][t];
+        at32(th + v * g.fs, base + z * lstride) = a[v][t];
       }
     }
   }
@@ -651,8 +659,10 @@ __global__ void __launch_bounds__((ColGeo<N, TX, RE>::THREADS))
 k_zpass_elastic(cx<T>* __restrict__ th, Geo g, ModelK m, const cx<T>* twz, cx<TE>* __restrict__ FEc,
                 int accumulate) {
   __shared__ cx<T> lds[N * ColGeo<N, TX, RE>::LD];
-  body_zpass_elastic<T, TE, N, TX, RE>(th, g, m, twz, FEc, accumulate, xcd_tile(blockIdx.x, gridDim.x),
-                                       threadIdx.x, lds);
+  __shared__ cx<T> twl[N];
+  for (int j = threadIdx.x; j < N; j += ColGeo<N, TX, RE>::THREADS) twl[j] = twz[j];
+  body_zpass_elastic<T, TE, N, TX, RE, false, true>(th, g, m, twl, FEc, accumulate,
+                                                    xcd_tile(blockIdx.x, gridDim.x), threadIdx.x, lds);
 }
 
 // ---- K-I: forward z-FFT of the AC driving force, F^E_eta = -L g~ ----------
