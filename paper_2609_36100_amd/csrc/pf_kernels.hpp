@@ -855,8 +855,11 @@ k_xpass_theta(const cx<T>* __restrict__ st, cx<T>* __restrict__ th, Geo g, const
               const cx<T>* twM) {
   using RG = RowGeo<M, RB>;
   __shared__ cx<T> lds[RB * RG::LD];
-  __shared__ cx<T> tM[M];
-  for (int j = threadIdx.x; j < M; j += RG::THREADS) tM[j] = twM[j];
+  __shared__ cx<T> tM[M], tN[M];
+  for (int j = threadIdx.x; j < M; j += RG::THREADS) {
+    tM[j] = twM[j];
+    tN[j] = twN[j];
+  }
   const int rl = threadIdx.x / RG::TL;
   const int bf = threadIdx.x % RG::TL;
   const int row = blockIdx.x * RB + rl;
@@ -868,16 +871,16 @@ k_xpass_theta(const cx<T>* __restrict__ st, cx<T>* __restrict__ th, Geo g, const
 #pragma unroll 1
   for (int v = 0; v < 3; ++v) {
     cx<T> a[RG::R0];
-    row_c2r_regs<T, M, RB, true>(raw, a, bf, rbuf, twN, tM);
+    row_c2r_regs<T, M, RB, true>(raw, a, bf, rbuf, tN, tM);
     if (v < 2) row_fetch<T, M, RB>(st + (2 + v) * g.fs + rb, rvalid, raw, bf);
 #pragma unroll
     for (int t = 0; t < RG::R0; ++t) a[t] = mk<T>(hfun(a[t].re), hfun(a[t].im));
-    row_r2c<T, M, RB, true>(a, th + v * g.fs + rb, rvalid, bf, rbuf, twN, tM);
+    row_r2c<T, M, RB, true>(a, th + v * g.fs + rb, rvalid, bf, rbuf, tN, tM);
   }
 }
 
 // K-G: g_v = h'(eta_v) (chi(c) + e_v) + 2 w eta_v (1 - eta_v)(1 - 2 eta_v).
-template <typename T, int M, int RB, bool GUARD = false>
+template <typename T, int M, int RB, bool GUARD = false, bool LB = false>
 __device__ inline void body_xpass_drive(const cx<T>* st, cx<T>* el, const Geo& g, const ModelK& m,
                                         const cx<T>* twN, const cx<T>* twM, int tile, int tid, cx<T>* lds) {
   using RG = RowGeo<M, RB>;
@@ -892,7 +895,9 @@ __device__ inline void body_xpass_drive(const cx<T>* st, cx<T>* el, const Geo& g
   cx<T> chi[RG::R0];
   {
     cx<T> a[RG::R0];
-    row_c2r<T, M, RB>(st + rb, rvalid, a, bf, rbuf, twN, twM, act);
+    cx<T> raw[RG::R0 + 1];
+    row_fetch<T, M, RB>(st + rb, rvalid, raw, bf, act);
+    row_c2r_regs<T, M, RB, LB>(raw, a, bf, rbuf, twN, twM, act);
 #pragma unroll
     for (int t = 0; t < RG::R0; ++t) {
       const T c0 = a[t].re, c1 = a[t].im;
@@ -906,9 +911,11 @@ __device__ inline void body_xpass_drive(const cx<T>* st, cx<T>* el, const Geo& g
       // FP64: both rows of this variant are requested before either is
       // transformed (8% faster at 512^3; 8% slower in FP32, kept apart there)
       cx<T> raw_e[RG::R0 + 1];
+      cx<T> raw_et[RG::R0 + 1];
+      row_fetch<T, M, RB>(st + (1 + v) * g.fs + rb, rvalid, raw_et, bf, act);
       row_fetch<T, M, RB>(el + v * g.fs + rb, rvalid, raw_e, bf, act);
-      row_c2r<T, M, RB>(st + (1 + v) * g.fs + rb, rvalid, et, bf, rbuf, twN, twM, act);
-      row_c2r_regs<T, M, RB>(raw_e, a, bf, rbuf, twN, twM, act);
+      row_c2r_regs<T, M, RB, LB>(raw_et, et, bf, rbuf, twN, twM, act);
+      row_c2r_regs<T, M, RB, LB>(raw_e, a, bf, rbuf, twN, twM, act);
     } else {
       row_c2r<T, M, RB>(st + (1 + v) * g.fs + rb, rvalid, et, bf, rbuf, twN, twM, act);
       row_c2r<T, M, RB>(el + v * g.fs + rb, rvalid, a, bf, rbuf, twN, twM, act);
@@ -920,7 +927,7 @@ __device__ inline void body_xpass_drive(const cx<T>* st, cx<T>* el, const Geo& g
       const T g1 = dhfun(e1) * (chi[t].im + a[t].im) + w2 * e1 * ((T)1 - e1) * ((T)1 - (T)2 * e1);
       a[t] = mk<T>(g0, g1);
     }
-    row_r2c<T, M, RB>(a, el + v * g.fs + rb, rvalid, bf, rbuf, twN, twM, act);
+    row_r2c<T, M, RB, LB>(a, el + v * g.fs + rb, rvalid, bf, rbuf, twN, twM, act);
   }
 }
 
@@ -936,14 +943,21 @@ k_xpass_drive(const cx<T>* __restrict__ st, cx<T>* __restrict__ el, Geo g, Model
               const cx<T>* twM) {
   using RG = RowGeo<M, RB>;
   __shared__ cx<T> lds[RB * RG::LD];
+  // both twiddle tables in LDS: no global load issued after a prefetch has
+  // to wait for it
+  __shared__ cx<T> tM[M], tN[M];
+  for (int j = threadIdx.x; j < M; j += RG::THREADS) {
+    tM[j] = twM[j];
+    tN[j] = twN[j];
+  }
   if constexpr (sizeof(T) == 8) {
     // FP64: the prefetch registers would cut the occupancy from 3 to 2 waves
-    // per SIMD; the plain body is used
-    body_xpass_drive<T, M, RB>(st, el, g, m, twN, twM, blockIdx.x, threadIdx.x, lds);
+    // per SIMD; the plain body runs with LDS-only barriers instead, so each
+    // variant's two rows load while nothing else waits for them and the
+    // stores of the previous variant stay in flight
+    body_xpass_drive<T, M, RB, false, true>(st, el, g, m, tN, tM, blockIdx.x, threadIdx.x, lds);
     return;
   }
-  __shared__ cx<T> tM[M];
-  for (int j = threadIdx.x; j < M; j += RG::THREADS) tM[j] = twM[j];
   const int rl = threadIdx.x / RG::TL;
   const int bf = threadIdx.x % RG::TL;
   const int row = blockIdx.x * RB + rl;
@@ -958,7 +972,7 @@ k_xpass_drive(const cx<T>* __restrict__ st, cx<T>* __restrict__ el, Geo g, Model
     row_fetch<T, M, RB>(st + rb, rvalid, raw_c, bf);
     row_fetch<T, M, RB>(st + g.fs + rb, rvalid, raw_eta, bf);
     cx<T> a[RG::R0];
-    row_c2r_regs<T, M, RB, true>(raw_c, a, bf, rbuf, twN, tM);
+    row_c2r_regs<T, M, RB, true>(raw_c, a, bf, rbuf, tN, tM);
     row_fetch<T, M, RB>(el + rb, rvalid, raw_e, bf);
 #pragma unroll
     for (int t = 0; t < RG::R0; ++t) {
@@ -970,8 +984,8 @@ k_xpass_drive(const cx<T>* __restrict__ st, cx<T>* __restrict__ el, Geo g, Model
 #pragma unroll 1
   for (int v = 0; v < 3; ++v) {
     cx<T> et[RG::R0], a[RG::R0];
-    row_c2r_regs<T, M, RB, true>(raw_eta, et, bf, rbuf, twN, tM);
-    row_c2r_regs<T, M, RB, true>(raw_e, a, bf, rbuf, twN, tM);
+    row_c2r_regs<T, M, RB, true>(raw_eta, et, bf, rbuf, tN, tM);
+    row_c2r_regs<T, M, RB, true>(raw_e, a, bf, rbuf, tN, tM);
     if (v < 2) row_fetch<T, M, RB>(st + (2 + v) * g.fs + rb, rvalid, raw_eta, bf);
 #pragma unroll
     for (int t = 0; t < RG::R0; ++t) {
@@ -980,7 +994,7 @@ k_xpass_drive(const cx<T>* __restrict__ st, cx<T>* __restrict__ el, Geo g, Model
       const T g1 = dhfun(e1) * (chi[t].im + a[t].im) + w2 * e1 * ((T)1 - e1) * ((T)1 - (T)2 * e1);
       a[t] = mk<T>(g0, g1);
     }
-    row_r2c<T, M, RB, true>(a, el + v * g.fs + rb, rvalid, bf, rbuf, twN, tM);
+    row_r2c<T, M, RB, true>(a, el + v * g.fs + rb, rvalid, bf, rbuf, tN, tM);
     if (v < 2) row_fetch<T, M, RB>(el + (1 + v) * g.fs + rb, rvalid, raw_e, bf);
   }
 }
