@@ -71,8 +71,10 @@ typedef enum { PF_IMEX_EULER = 1, PF_ARK2 = 2, PF_ARK324L = 3, PF_ARK436L = 4 } 
  *   dc/dt = div(M grad dF/dc) (Eq. x_gov), deta_v/dt = -L dF/deta_v (Eq. phi_gov).
  * Split: f^I_c = -M k^2 (a_c + kappa_c k^2) c~ with a_c = 2W when
  *   implicit_bulk_c = 1 (default) else 0; f^I_eta = -L kappa_eta k^2 eta~.
- * Sizes: nx, ny, nz must each be a multiple of 8 with no prime factor above
- *   5, between 8 and 512 (see pf_size_supported). */
+ * Sizes: nx, ny, nz each one of the compiled line lengths 8, 16, 24, 32, 40,
+ *   48, 56, 64, 80, 96, 128, 160, 168, 192, 256, 320, 336, 384, 504, 512
+ *   (multiples of 8 with prime factors 2, 3, 5, 7; the factor-7 lengths are
+ *   the paper's 168^3, 336^3 and 504^3 grids); see pf_size_supported. */
 typedef struct {
   int32_t nx, ny, nz;
   double dx;
@@ -109,7 +111,8 @@ typedef struct {
  * Never fails for non-NULL p. */
 pf_status pf_default_params(pf_params* p);
 
-/* Returns 1 if n is a supported grid length, else 0. */
+/* Returns 1 if n is a supported grid length (the list under pf_params),
+ * else 0. */
 int32_t pf_size_supported(int32_t n);
 
 /* Creates a context for the grid and model in *p on the current device and

@@ -1,4 +1,4 @@
-// Radix-2/3/4/5/8 Stockham FFT building blocks for gfx950.
+// Radix-2/3/4/5/6/7/8 Stockham FFT building blocks for gfx950.
 //
 // The paper moves every field between real and reciprocal space with 3D FFTs
 // (Methods, "MEUMAPPS C++ and the MEUMAPPS-SS application"; "Scalable,
@@ -151,6 +151,59 @@ struct Dft<5, S, T> {
   }
 };
 
+// Six points as two 3-point DFTs of the even and odd samples combined with
+// w_6^{S k}: X_k = E_{k mod 3} + w_6^{S k} O_{k mod 3}.
+template <int S, typename T>
+struct Dft<6, S, T> {
+  __host__ __device__ static inline void run(cx<T>* a) {
+    cx<T> e[3] = {a[0], a[2], a[4]};
+    cx<T> o[3] = {a[1], a[3], a[5]};
+    Dft<3, S, T>::run(e);
+    Dft<3, S, T>::run(o);
+    const T s3 = (T)0.86602540378443864676372317075293618347;  // sin(pi/3)
+    const cx<T> o1 = cmul(o[1], mk<T>((T)0.5, (T)S * s3));     // exp(S i pi/3)
+    const cx<T> o2 = cmul(o[2], mk<T>((T)-0.5, (T)S * s3));    // exp(S i 2pi/3)
+    a[0] = e[0] + o[0];
+    a[3] = e[0] - o[0];
+    a[1] = e[1] + o1;
+    a[4] = e[1] - o1;
+    a[2] = e[2] + o2;
+    a[5] = e[2] - o2;
+  }
+};
+
+// Seven points: pair n with 7 - n, X_k = r_k + S i q_k and X_{7-k} = r_k - S i q_k
+// with r_k = a_0 + sum_j cos(2 pi j k/7) (a_j + a_{7-j}) and
+// q_k = sum_j sin(2 pi j k/7) (a_j - a_{7-j}), j = 1..3.
+template <int S, typename T>
+struct Dft<7, S, T> {
+  __host__ __device__ static inline void run(cx<T>* a) {
+    const T c1 = (T)0.62348980185873353052500488400423981063;   // cos(2 pi/7)
+    const T c2 = (T)-0.22252093395631440428890256449679475947;  // cos(4 pi/7)
+    const T c3 = (T)-0.90096886790241912623610231950744505117;  // cos(6 pi/7)
+    const T s1 = (T)0.78183148246802980870844452667405775023;   // sin(2 pi/7)
+    const T s2 = (T)0.97492791218182360701813168299393121723;   // sin(4 pi/7)
+    const T s3 = (T)0.43388373911755812047576833284835875461;   // sin(6 pi/7)
+    cx<T> p1 = a[1] + a[6], m1 = a[1] - a[6];
+    cx<T> p2 = a[2] + a[5], m2 = a[2] - a[5];
+    cx<T> p3 = a[3] + a[4], m3 = a[3] - a[4];
+    cx<T> x0 = a[0];
+    cx<T> r1 = x0 + c1 * p1 + c2 * p2 + c3 * p3;
+    cx<T> r2 = x0 + c2 * p1 + c3 * p2 + c1 * p3;
+    cx<T> r3 = x0 + c3 * p1 + c1 * p2 + c2 * p3;
+    cx<T> i1 = mul_si<S>(s1 * m1 + s2 * m2 + s3 * m3);
+    cx<T> i2 = mul_si<S>(s2 * m1 - s3 * m2 - s1 * m3);
+    cx<T> i3 = mul_si<S>(s3 * m1 - s1 * m2 + s2 * m3);
+    a[0] = x0 + p1 + p2 + p3;
+    a[1] = r1 + i1;
+    a[6] = r1 - i1;
+    a[2] = r2 + i2;
+    a[5] = r2 - i2;
+    a[3] = r3 + i3;
+    a[4] = r3 - i3;
+  }
+};
+
 template <int R, int S, typename T>
 __host__ __device__ inline void dft(cx<T>* a) {
   Dft<R, S, T>::run(a);
@@ -166,16 +219,23 @@ struct Plan {
 
 // Radix sequence for a line of length n whose first and last radix (the "end"
 // radix, at most remax) are equal.  Middle factors are taken greedily from
-// {8, 4, 2, 3, 5}.  ok = 0 when n has no such factorisation.
+// {8, 4, 2, 3, 5, 7}.  ok = 0 when n has no such factorisation.
 __host__ __device__ constexpr Plan plan(int n, int remax = 8) {
   Plan P{n, 0, {0, 0, 0, 0, 0, 0, 0, 0}, 0};
-  if (n == 3 || n == 5 || ((n == 2 || n == 4 || n == 8) && n <= remax)) {
+  if (n == 3 || n == 5 || n == 7 || ((n == 2 || n == 4 || n == 8) && n <= remax)) {
     P.np = 1;
     P.r[0] = n;
     P.ok = 1;
     return P;
   }
   int re = (remax >= 8 && n % 64 == 0) ? 8 : (remax >= 4 && n % 16 == 0) ? 4 : (n % 4 == 0) ? 2 : 0;
+  // where radix 2 would be the alternative: radix-6 ends when 36 | n, else
+  // radix-3 ends when 9 | n (504 = 6 * 14 * 6: four passes instead of six and a
+  // third of the threads per line)
+  if (re == 2 && remax >= 6 && n % 36 == 0)
+    re = 6;
+  else if (re == 2 && remax >= 3 && n % 9 == 0)
+    re = 3;
   if (re == 0) return P;
   int m = n / (re * re);
   int mid[6] = {0, 0, 0, 0, 0, 0};
@@ -185,6 +245,7 @@ __host__ __device__ constexpr Plan plan(int n, int remax = 8) {
   while (m % 2 == 0 && nm < 6) { mid[nm++] = 2; m /= 2; }
   while (m % 3 == 0 && nm < 6) { mid[nm++] = 3; m /= 3; }
   while (m % 5 == 0 && nm < 6) { mid[nm++] = 5; m /= 5; }
+  while (m % 7 == 0 && nm < 6) { mid[nm++] = 7; m /= 7; }
   if (m != 1) return P;
   P.r[0] = re;
   for (int i = 0; i < nm; ++i) P.r[1 + i] = mid[i];
@@ -244,6 +305,8 @@ __host__ __device__ inline void butterfly_rt(int R, int n, int p, int b, const c
     case 3: butterfly<3, S, T>(n, p, b, tw, in, out); break;
     case 4: butterfly<4, S, T>(n, p, b, tw, in, out); break;
     case 5: butterfly<5, S, T>(n, p, b, tw, in, out); break;
+    case 6: butterfly<6, S, T>(n, p, b, tw, in, out); break;
+    case 7: butterfly<7, S, T>(n, p, b, tw, in, out); break;
     case 8: butterfly<8, S, T>(n, p, b, tw, in, out); break;
     default: break;
   }

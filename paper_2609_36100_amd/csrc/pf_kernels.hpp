@@ -115,6 +115,15 @@ __device__ inline void apply_twiddles(cx<T>* a, const cx<T>* tw, int j) {
       a[3] = cmul(a[3], w3);
       if constexpr (R == 5) {
         a[4] = cmul(a[4], cmul(w2, w2));
+      } else if constexpr (R == 6) {
+        const cx<T> w4 = twiddle<S>(tw, 4 * j);
+        a[4] = cmul(a[4], w4);
+        a[5] = cmul(a[5], cmul(w4, w1));
+      } else if constexpr (R == 7) {
+        const cx<T> w4 = twiddle<S>(tw, 4 * j);
+        a[4] = cmul(a[4], w4);
+        a[5] = cmul(a[5], cmul(w4, w1));
+        a[6] = cmul(a[6], cmul(w4, w2));
       } else if constexpr (R == 8) {
         const cx<T> w4 = twiddle<S>(tw, 4 * j);
         a[4] = cmul(a[4], w4);

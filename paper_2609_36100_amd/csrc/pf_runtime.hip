@@ -25,8 +25,12 @@ using namespace pf;
 
 // ---- supported line lengths --------------------------------------------
 // Column passes (y, z) take N; row passes (x) take M = nx / 2.
-#define PF_COL_SIZES(X) X(8) X(16) X(24) X(32) X(40) X(48) X(64) X(80) X(96) X(128) X(160) X(192) X(256) X(320) X(384) X(512)
-#define PF_ROW_SIZES(X) X(4) X(8) X(12) X(16) X(20) X(24) X(32) X(40) X(48) X(64) X(80) X(96) X(128) X(160) X(192) X(256)
+#define PF_COL_SIZES(X)                                                                                  \
+  X(8) X(16) X(24) X(32) X(40) X(48) X(56) X(64) X(80) X(96) X(128) X(160) X(168) X(192) X(256) X(320) X(336) \
+  X(384) X(504) X(512)
+#define PF_ROW_SIZES(X)                                                                                         \
+  X(4) X(8) X(12) X(16) X(20) X(24) X(28) X(32) X(40) X(48) X(64) X(80) X(84) X(96) X(128) X(160) X(168) X(192) \
+  X(252) X(256)
 
 template <class F>
 static bool col_dispatch(int n, F&& f) {
@@ -77,6 +81,9 @@ constexpr int col_tx(int n, int kind, int elem_bytes, int v) {
   int tx = seg / elem_bytes;
   if (tx < 1) tx = 1;
   while (tx * line_threads(n, col_re(kind)) < 64 && tx < 16) tx *= 2;
+  // long lines with small end radices (504 in the elastic pass: 168 threads
+  // per line) stay within 1024 threads per work-group
+  while (tx > 1 && tx * line_threads(n, col_re(kind)) > 1024) tx /= 2;
   return tx;
 }
 // Whether the wave-specialised column FFT (variant 2 of "colfft") exists for

@@ -1,5 +1,5 @@
 // Host-side check of the FFT building blocks used by the gfx950 kernels:
-// compile-time plans, radix-2/3/4/5/8 DFTs, the Stockham butterfly index and
+// compile-time plans, radix-2/3/4/5/6/7/8 DFTs, the Stockham butterfly index and
 // twiddle arithmetic, and the real<->half-complex packing.  Runs each line
 // length through the plan's passes on the CPU and compares with a naive DFT
 // evaluated in long double.  Prints one line per case: "<case> <n> <relerr>".
@@ -57,7 +57,8 @@ static double naive_err(const std::vector<C>& in, const std::vector<C>& out, int
 }
 
 int main() {
-  const int sizes[] = {4, 8, 12, 16, 20, 24, 32, 40, 48, 64, 80, 96, 128, 160, 192, 256, 320, 384, 512};
+  const int sizes[] = {4,  7,  8,   12,  16,  20,  24,  28,  32,  36,  40,  48,  56,  64,  72,  80, 84,
+                       96, 128, 160, 168, 192, 252, 256, 320, 336, 384, 504, 512};
   srand(7);
   int fails = 0;
   for (int n : sizes) {
@@ -84,7 +85,7 @@ int main() {
     printf("inv %d %.3e\n", n, naive_err(x, g, +1));
   }
   // real transforms of length N = 2M via packed M-point complex FFTs
-  const int rsizes[] = {8, 16, 24, 32, 40, 48, 64, 96, 128, 192, 256, 512};
+  const int rsizes[] = {8, 16, 24, 32, 40, 48, 56, 64, 72, 96, 128, 168, 192, 256, 336, 504, 512};
   for (int N : rsizes) {
     const int M = N / 2;
     std::vector<double> xr(N);

@@ -34,9 +34,10 @@ def test_host_only_entry_points():
     assert L.pf_default_params(ctypes.byref(p)) == 0
     assert (p.C11, p.C12, p.C44) == (250.0, 150.0, 120.0)
     assert p.eps_star[1][1] == 0.0286 and p.eps_star[1][0] == 0.0067
-    for n in (8, 16, 24, 32, 48, 64, 96, 128, 256, 512):
+    for n in (8, 16, 24, 32, 48, 56, 64, 96, 128, 168, 256, 336, 504, 512):
         assert L.pf_size_supported(n) == 1, n
-    for n in (6, 10, 12, 168, 336, 504, 1024, 7, 0, -8):
+    # not a multiple of 8, a prime factor above 7, beyond 512, or not in the compiled set
+    for n in (6, 10, 12, 28, 88, 104, 112, 144, 1024, 7, 0, -8):
         assert L.pf_size_supported(n) == 0, n
     assert L.pf_status_string(-4) == b"PF_ERR_UNSUPPORTED_SIZE"
     assert L.pf_status_string(12345) == b"PF_UNKNOWN_STATUS"
@@ -63,7 +64,7 @@ def test_argument_checks_precede_any_device_work():
     assert init(method=_lib.PF_IMEX_EULER, adaptive=1) == -1      # no embedding to control with
     assert init(method=_lib.PF_ARK2, adaptive=1, atol=0.0) == -1
     assert init(mean_strain_mode=2) == -1
-    assert init(nx=7) == -4 and init(nz=168) == -4
+    assert init(nx=7) == -4 and init(nz=88) == -4
     # ensembles: cubic supported sizes, one embedded method, one precision
     arr = (_lib.Params * 2)()
     arr[0] = _lib.make_params(32, None)
