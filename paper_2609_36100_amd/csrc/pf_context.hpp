@@ -189,6 +189,7 @@ struct pf_ctx {
   pf::ModelK mk;
   pf::ArkTable tab;
   bool fe_need[6], fi_need[6];
+  bool fi0_derived = false;  // F^I_1 = L y recomputed, never stored (explicit first stage)
   int mixed = 0;
 
   bool owns = true;  // false for views whose buffers belong to an ensemble

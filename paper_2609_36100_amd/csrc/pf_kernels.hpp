@@ -280,6 +280,10 @@ struct StageArgs {
   double gdt;              // dt * A^I_ii
   cx<double>* FI_out;      // F^I_i (may be null when unused)
   cx<TE>* FEc_out;         // split A: explicit CH part from z_c (may be null)
+  // 1: F^I_1 is not read from FI[0] but formed as L(k) y.  With an explicit
+  // first stage (A^I_11 = 0) the first stage value is the state itself, so
+  // F^I_1 = L y exactly and the array is never stored.
+  int fi0_from_y;
 };
 
 // Stage combination for one element (Eq. ARK_stage restricted to the
@@ -292,7 +296,10 @@ __device__ inline cx<double> stage_value(const StageArgs<TE>& sa, long long idx,
 #pragma unroll
   for (int j = 0; j < NP; ++j) {
     fe[j] = sa.cE[j] != 0.0 ? to_d(sa.FE[j][idx]) : mk(0.0, 0.0);
-    fi[j] = sa.cI[j] != 0.0 ? sa.FI[j][idx] : mk(0.0, 0.0);
+    if (j == 0 && sa.fi0_from_y)
+      fi[0] = L * r;
+    else
+      fi[j] = sa.cI[j] != 0.0 ? sa.FI[j][idx] : mk(0.0, 0.0);
   }
 #pragma unroll
   for (int j = 0; j < NP; ++j) r = r + (sa.cE[j] * fe[j] + sa.cI[j] * fi[j]);
@@ -371,12 +378,13 @@ __global__ void __launch_bounds__(256) k_combine(StageArgs<TE> sa, Geo g, ModelK
     const double kx = x * g.kfx, ky = mode_of(y, g.ny) * g.kfy, kz = mode_of(z, g.nz) * g.kfz;
     const double k2 = kx * kx + ky * ky + kz * kz;
     const long long idx = fr * g.P + x;
-    cx<double> r = sa.y[idx];
+    const double L = lsym(m, f, k2);
+    const cx<double> y0 = sa.y[idx];
+    cx<double> r = y0;
     for (int j = 0; j < sa.nprev; ++j) {
       if (sa.cE[j] != 0.0) r = r + sa.cE[j] * to_d(sa.FE[j][idx]);
-      if (sa.cI[j] != 0.0) r = r + sa.cI[j] * sa.FI[j][idx];
+      if (sa.cI[j] != 0.0) r = r + sa.cI[j] * ((j == 0 && sa.fi0_from_y) ? L * y0 : sa.FI[j][idx]);
     }
-    const double L = lsym(m, f, k2);
     const cx<double> zz = (sa.gdt != 0.0) ? (1.0 / (1.0 - sa.gdt * L)) * r : r;
     if (sa.FI_out) sa.FI_out[idx] = L * zz;
   }
@@ -1089,21 +1097,23 @@ struct FinArgs {
   double dE[6], dI[6];   // error weights (b - b~) times dt
   int s;
   int want_err;
+  int fi0_from_y;         // F^I_1 = L(k) y (explicit first stage), FI[0] unread
   double rtol, atol, sc;  // sc = 1/sqrt(N^3)
   double* partial;        // [2 * gridDim.x]: sum of squares, non-finite count
 };
 
 template <typename TE>
-__global__ void __launch_bounds__(256) k_finalize(FinArgs<TE> fa, Geo g) {
+__global__ void __launch_bounds__(256) k_finalize(FinArgs<TE> fa, Geo g, ModelK m) {
   __shared__ double sh[16];
-  const long long nrow = (long long)g.nz * g.ny;
-  const long long total = 4 * nrow * g.nxh;
+  // 32-bit indices: 4 nz ny (nx/2+1) < 2^31 on every supported grid
+  const unsigned nrow = (unsigned)(g.nz * g.ny);
+  const unsigned nxh = (unsigned)g.nxh;
+  const unsigned total = 4u * nrow * nxh;
   double acc = 0.0, bad = 0.0;
-  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
-       i += (long long)gridDim.x * blockDim.x) {
-    const int x = (int)(i % g.nxh);
-    const long long fr = i / g.nxh;  // f * nrow + row
-    const long long idx = fr * g.P + x;
+  for (unsigned i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) {
+    const unsigned x = i % nxh;
+    const unsigned fr = i / nxh;  // f * nrow + row
+    const long long idx = (long long)fr * g.P + x;
     const cx<double> y0 = fa.y[idx];
     // every stage array this step reads is loaded before any is used, so the
     // loads of one element are in flight together (unused weights are zero)
@@ -1112,8 +1122,15 @@ __global__ void __launch_bounds__(256) k_finalize(FinArgs<TE> fa, Geo g) {
     for (int j = 0; j < 6; ++j) {
       const bool hasI = j < fa.s && (fa.bI[j] != 0.0 || (fa.want_err && fa.dI[j] != 0.0));
       const bool hasE = j < fa.s && (fa.bE[j] != 0.0 || (fa.want_err && fa.dE[j] != 0.0));
-      fi[j] = hasI ? fa.FI[j][idx] : mk(0.0, 0.0);
+      fi[j] = (hasI && !(j == 0 && fa.fi0_from_y)) ? fa.FI[j][idx] : mk(0.0, 0.0);
       fe[j] = hasE ? to_d(fa.FE[j][idx]) : mk(0.0, 0.0);
+    }
+    if (fa.fi0_from_y) {
+      const unsigned f = fr / nrow, row = fr % nrow;
+      const int yy = (int)(row % (unsigned)g.ny), z = (int)(row / (unsigned)g.ny);
+      const double kx = (int)x * g.kfx, ky = mode_of(yy, g.ny) * g.kfy, kz = mode_of(z, g.nz) * g.kfz;
+      const double k2 = kx * kx + ky * ky + kz * kz;
+      fi[0] = lsym(m, (int)f, k2) * y0;
     }
     cx<double> inc = mk(0.0, 0.0), err = mk(0.0, 0.0);
 #pragma unroll
@@ -1126,7 +1143,7 @@ __global__ void __launch_bounds__(256) k_finalize(FinArgs<TE> fa, Geo g) {
     fa.ynew[idx] = yn;
     if (!isfinite(yn.re) || !isfinite(yn.im)) bad += 1.0;
     if (fa.want_err) {
-      const double mult = (x == 0 || 2 * x == g.nx) ? 1.0 : 2.0;
+      const double mult = (x == 0 || 2 * (int)x == g.nx) ? 1.0 : 2.0;
       const double ay = sqrt(y0.re * y0.re + y0.im * y0.im) * fa.sc;
       const double wgt = 1.0 / (fa.rtol * ay + fa.atol);
       const double e2 = (err.re * err.re + err.im * err.im) * fa.sc * fa.sc;

@@ -395,7 +395,7 @@ static pf_status run_stage(pf_ctx* c, const StageArgs<TE>& sa, bool need_rhs, cx
   const double fT = nv * sizeof(cx<T>), fE = nv * sizeof(cx<TE>), f64 = nv * sizeof(cx<double>);
   double b_stage = 4 * f64;  // state read
   for (int j = 0; j < sa.nprev; ++j)
-    b_stage += 4 * ((sa.cE[j] != 0.0 ? fE : 0.0) + (sa.cI[j] != 0.0 ? f64 : 0.0));
+    b_stage += 4 * ((sa.cE[j] != 0.0 ? fE : 0.0) + ((sa.cI[j] != 0.0 && !(j == 0 && sa.fi0_from_y)) ? f64 : 0.0));
   b_stage += (sa.FI_out ? 4 * f64 : 0.0) + (sa.FEc_out ? fE : 0.0) + (need_rhs ? 4 * fT : 0.0);
   prof_begin(c);
   if (!launch_stage_invz<T, TE>(c, sa, T1, need_rhs ? 1 : 0)) return PF_ERR_UNSUPPORTED_SIZE;
@@ -449,7 +449,8 @@ static pf_status stages_and_finalize(pf_ctx* c, double dt, int* n_rhs) {
     }
     sa.nprev = i;
     sa.gdt = dt * tb.AI[i][i];
-    sa.FI_out = c->fi_need[i] ? c->FI[i] : nullptr;
+    sa.fi0_from_y = c->fi0_derived ? 1 : 0;
+    sa.FI_out = (c->fi_need[i] && !(i == 0 && c->fi0_derived)) ? c->FI[i] : nullptr;
     const bool need_rhs = c->fe_need[i];
     sa.FEc_out = (need_rhs && c->mk.fEa != 0.0) ? (cx<TE>*)c->FE[i] : nullptr;
     pf_status s = run_stage<T, TE>(c, sa, need_rhs, (cx<TE>*)c->FE[i]);
@@ -470,6 +471,7 @@ static pf_status stages_and_finalize(pf_ctx* c, double dt, int* n_rhs) {
   }
   fa.s = tb.s;
   fa.want_err = tb.has_emb;
+  fa.fi0_from_y = c->fi0_derived ? 1 : 0;
   fa.rtol = c->p.rtol;
   fa.atol = c->p.atol;
   fa.sc = 1.0 / std::sqrt((double)c->g.nx * c->g.ny * c->g.nz);
@@ -478,11 +480,11 @@ static pf_status stages_and_finalize(pf_ctx* c, double dt, int* n_rhs) {
   double b_fin = 2.0 * 4 * c->g.nz * (double)c->g.ny * c->g.nxh * sizeof(cx<double>);
   for (int j = 0; j < tb.s; ++j) {
     const double nv = 4.0 * c->g.nz * (double)c->g.ny * c->g.nxh;
-    if (fa.bI[j] != 0.0 || fa.dI[j] != 0.0) b_fin += nv * sizeof(cx<double>);
+    if ((fa.bI[j] != 0.0 || fa.dI[j] != 0.0) && !(j == 0 && fa.fi0_from_y)) b_fin += nv * sizeof(cx<double>);
     if (fa.bE[j] != 0.0 || fa.dE[j] != 0.0) b_fin += nv * sizeof(cx<TE>);
   }
   prof_begin(c);
-  k_finalize<TE><<<dim3(c->nblk_red), dim3(256), 0, c->stream>>>(fa, c->g);
+  k_finalize<TE><<<dim3(c->nblk_red), dim3(256), 0, c->stream>>>(fa, c->g, c->mk);
   k_reduce_pairs<<<dim3(1), dim3(256), 0, c->stream>>>(c->partial, c->nblk_red, c->red);
   prof_end(c, KC_FINAL, b_fin);
   if (hipGetLastError() != hipSuccess) return PF_ERR_HIP;
@@ -560,6 +562,8 @@ void ctx_setup(pf_ctx* c, const pf_params* p, hipStream_t stream) {
     c->fe_need[i] = fe_needed(c->tab, i);
     c->fi_need[i] = fi_needed(c->tab, i);
   }
+  // explicit first stage: its value is the state, F^I_1 = L y is formed where used
+  c->fi0_derived = c->tab.AI[0][0] == 0.0 && c->fi_need[0];
   std::memset(&c->st, 0, sizeof(c->st));
   c->dt_next = p->dt0;
   c->st.dt_min_seen = 1e300;
