@@ -69,11 +69,13 @@ struct EState {
 struct StageCoef {
   double aE[6], aI[6], aii;
   int fi_out, fe_need;
+  int fi0_from_y;  // F^I_1 = L(k) y formed in place (explicit first stage)
 };
 
 struct FinCoef {
   double bE[6], bI[6], dE[6], dI[6];
   int s, want_err;
+  int fi0_from_y;  // as in StageCoef
 };
 
 // kernel kinds with their own work list and work-group size
@@ -138,7 +140,7 @@ __global__ void __launch_bounds__(EB) kb_stage(const EMemb<T, TE>* mem, const ES
   sa.nprev = NP;
   sa.gdt = dt * sc.aii;
   sa.FI_out = sc.fi_out ? e.FI[NP] : nullptr;
-  sa.fi0_from_y = 0;
+  sa.fi0_from_y = sc.fi0_from_y;
   sa.FEc_out = e.mk.fEa != 0.0 ? e.FE[NP] : nullptr;
   switch (e.g.nz) {
 #define PF_C(N)                                                                                       \
@@ -265,7 +267,8 @@ __global__ void __launch_bounds__(256) kb_finalize(const EMemb<T, TE>* mem, cons
   double acc = 0.0, bad = 0.0;
   for (long long i = lb * 256LL + threadIdx.x; i < total; i += 256LL * nb) {
     const int x = (int)(i % g.nxh);
-    const long long idx = (i / g.nxh) * g.P + x;
+    const long long fr = i / g.nxh;  // f * nrow + row
+    const long long idx = fr * g.P + x;
     const cx<double> y0 = y[idx];
     // all the stage loads of one element are issued before any is used
     cx<double> fi[6], fe[6];
@@ -273,8 +276,16 @@ __global__ void __launch_bounds__(256) kb_finalize(const EMemb<T, TE>* mem, cons
     for (int j = 0; j < 6; ++j) {
       const bool hasI = j < fc.s && (fc.bI[j] != 0.0 || (fc.want_err && fc.dI[j] != 0.0));
       const bool hasE = j < fc.s && (fc.bE[j] != 0.0 || (fc.want_err && fc.dE[j] != 0.0));
-      fi[j] = hasI ? e.FI[j][idx] : mk(0.0, 0.0);
+      fi[j] = (hasI && !(j == 0 && fc.fi0_from_y)) ? e.FI[j][idx] : mk(0.0, 0.0);
       fe[j] = hasE ? to_d(e.FE[j][idx]) : mk(0.0, 0.0);
+    }
+    if (fc.fi0_from_y) {
+      const int f = (int)(fr / nrow);
+      const int row = (int)(fr % nrow);
+      const int yy = row % g.ny, z = row / g.ny;
+      const double kx = x * g.kfx, ky = mode_of(yy, g.ny) * g.kfy, kz = mode_of(z, g.nz) * g.kfz;
+      const double k2 = kx * kx + ky * ky + kz * kz;
+      fi[0] = lsym(e.mk, f, k2) * y0;
     }
     cx<double> inc = mk(0.0, 0.0), err = mk(0.0, 0.0);
 #pragma unroll
@@ -388,6 +399,7 @@ struct pf_ens {
   double tune_ms[EK_COUNT][2] = {{0}};
   ArkTable tab;
   bool fe_need[6], fi_need[6];
+  bool fi0_derived = false;  // explicit first stage: F^I_1 = L y, never stored
   hipGraphExec_t exec = nullptr;
   hipGraph_t graph = nullptr;
   std::map<int, std::pair<cx<double>*, cx<double>*>> tw64;  // N -> (w_N, w_{N/2})
@@ -475,7 +487,8 @@ static void launch_kind(pf_ens* E, int kind, int stage) {
           sc.aI[j] = (j < stage && E->fi_need[j]) ? E->tab.AI[stage][j] : 0.0;
         }
         sc.aii = E->tab.AI[stage][stage];
-        sc.fi_out = E->fi_need[stage] ? 1 : 0;
+        sc.fi0_from_y = E->fi0_derived ? 1 : 0;
+        sc.fi_out = (E->fi_need[stage] && !(stage == 0 && E->fi0_derived)) ? 1 : 0;
         switch (stage) {
           case 0: kb_stage<T, TE, EB, 0><<<nb, EB, 0, s>>>(mem, E->st_dev, st, E->M, sc); break;
           case 1: kb_stage<T, TE, EB, 1><<<nb, EB, 0, s>>>(mem, E->st_dev, st, E->M, sc); break;
@@ -538,6 +551,7 @@ static void enqueue_step(pf_ens* E) {
   }
   fc.s = tb.s;
   fc.want_err = tb.has_emb;
+  fc.fi0_from_y = E->fi0_derived ? 1 : 0;
   const EMemb<T, TE>* mem = (const EMemb<T, TE>*)E->mem_dev;
   kb_finalize<T, TE><<<E->nfin, 256, 0, E->stream>>>(mem, E->st_dev, E->fin_start, E->M, fc, E->partial);
   kb_control<T, TE><<<E->M, 256, 0, E->stream>>>(mem, E->st_dev, E->fin_start, E->partial, tb.emb_order,
@@ -631,6 +645,7 @@ pf_status pf_ensemble_init(int32_t n, const pf_params* per_member, void* stream,
     E->fe_need[i] = fe_needed(E->tab, i);
     E->fi_need[i] = fi_needed(E->tab, i);
   }
+  E->fi0_derived = E->tab.AI[0][0] == 0.0 && E->fi_need[0];
   pf_status s = PF_OK;
   // per-size twiddle tables
   for (int m = 0; m < n && s == PF_OK; ++m) {
