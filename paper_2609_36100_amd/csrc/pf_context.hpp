@@ -190,6 +190,9 @@ struct pf_ctx {
   pf::ArkTable tab;
   bool fe_need[6], fi_need[6];
   bool fi0_derived = false;  // F^I_1 = L y recomputed, never stored (explicit first stage)
+  // the last stage forms the update and error sums (U into the last stage's
+  // F^I buffer, E into the unused F^I_1 buffer); the update reads y, U, E, F^E_s
+  bool fold_last = false;
   int mixed = 0;
 
   bool owns = true;  // false for views whose buffers belong to an ensemble

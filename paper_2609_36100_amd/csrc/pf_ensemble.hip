@@ -141,6 +141,8 @@ __global__ void __launch_bounds__(EB) kb_stage(const EMemb<T, TE>* mem, const ES
   sa.gdt = dt * sc.aii;
   sa.FI_out = sc.fi_out ? e.FI[NP] : nullptr;
   sa.fi0_from_y = sc.fi0_from_y;
+  sa.U_out = nullptr;  // the ensemble update reads the stage arrays itself
+  sa.E_out = nullptr;
   sa.FEc_out = e.mk.fEa != 0.0 ? e.FE[NP] : nullptr;
   switch (e.g.nz) {
 #define PF_C(N)                                                                                       \

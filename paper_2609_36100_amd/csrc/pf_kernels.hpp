@@ -284,6 +284,17 @@ struct StageArgs {
   // first stage (A^I_11 = 0) the first stage value is the state itself, so
   // F^I_1 = L y exactly and the array is never stored.
   int fi0_from_y;
+  // Last stage of an embedded method only (U_out non-null): the update and
+  // error sums of the step (Eqs. ARK_method, ARK_embedding) over every term
+  // but the last stage's explicit derivative are formed here, from values
+  // this kernel loads anyway plus the last stage's own F^I (never stored):
+  //   U = y + sum_{j<i} (uE_j F^E_j + uI_j F^I_j) + uIs F^I_i,
+  //   E =     sum_{j<i} (eE_j F^E_j + eI_j F^I_j) + eIs F^I_i,
+  // with u = dt b and e = dt (b - b~).  The update then reads y, U, E, F^E_i.
+  cx<double>* U_out;
+  cx<double>* E_out;
+  double uE[6], uI[6], eE[6], eI[6];
+  double uIs, eIs;
 };
 
 // Stage combination for one element (Eq. ARK_stage restricted to the
@@ -291,21 +302,36 @@ struct StageArgs {
 template <typename TE, int NP>
 __device__ inline cx<double> stage_value(const StageArgs<TE>& sa, long long idx, double L, cx<double>* FIo,
                                          cx<TE>* FEo, double fea_k2, int f) {
-  cx<double> r = sa.y[idx];
+  const cx<double> y0 = sa.y[idx];
+  const bool fold = sa.U_out != nullptr;  // uniform
   cx<double> fe[NP > 0 ? NP : 1], fi[NP > 0 ? NP : 1];
 #pragma unroll
   for (int j = 0; j < NP; ++j) {
-    fe[j] = sa.cE[j] != 0.0 ? to_d(sa.FE[j][idx]) : mk(0.0, 0.0);
+    const bool useE = sa.cE[j] != 0.0 || (fold && (sa.uE[j] != 0.0 || sa.eE[j] != 0.0));
+    const bool useI = sa.cI[j] != 0.0 || (fold && (sa.uI[j] != 0.0 || sa.eI[j] != 0.0));
+    fe[j] = useE ? to_d(sa.FE[j][idx]) : mk(0.0, 0.0);
     if (j == 0 && sa.fi0_from_y)
-      fi[0] = L * r;
+      fi[0] = L * y0;
     else
-      fi[j] = sa.cI[j] != 0.0 ? sa.FI[j][idx] : mk(0.0, 0.0);
+      fi[j] = useI ? sa.FI[j][idx] : mk(0.0, 0.0);
   }
+  cx<double> r = y0;
 #pragma unroll
   for (int j = 0; j < NP; ++j) r = r + (sa.cE[j] * fe[j] + sa.cI[j] * fi[j]);
   const cx<double> zz = (sa.gdt != 0.0) ? (1.0 / (1.0 - sa.gdt * L)) * r : r;
-  if (FIo) FIo[idx] = L * zz;
+  const cx<double> fin = L * zz;
+  if (FIo) FIo[idx] = fin;
   if (f == 0 && FEo) FEo[idx] = to_t<TE>((-fea_k2) * zz);
+  if (fold) {
+    cx<double> u = y0, e = mk(0.0, 0.0);
+#pragma unroll
+    for (int j = 0; j < NP; ++j) {
+      u = u + (sa.uE[j] * fe[j] + sa.uI[j] * fi[j]);
+      e = e + (sa.eE[j] * fe[j] + sa.eI[j] * fi[j]);
+    }
+    sa.U_out[idx] = u + sa.uIs * fin;
+    sa.E_out[idx] = e + sa.eIs * fin;
+  }
   return zz;
 }
 
@@ -1098,6 +1124,10 @@ struct FinArgs {
   int s;
   int want_err;
   int fi0_from_y;         // F^I_1 = L(k) y (explicit first stage), FI[0] unread
+  // partial sums from the last stage (null: off): y_new = U + sum(...),
+  // error = E + sum(...); the weights then hold only the last stage's F^E term
+  const cx<double>* U;
+  const cx<double>* E;
   double rtol, atol, sc;  // sc = 1/sqrt(N^3)
   double* partial;        // [2 * gridDim.x]: sum of squares, non-finite count
 };
@@ -1132,14 +1162,14 @@ __global__ void __launch_bounds__(256) k_finalize(FinArgs<TE> fa, Geo g, ModelK 
       const double k2 = kx * kx + ky * ky + kz * kz;
       fi[0] = lsym(m, (int)f, k2) * y0;
     }
-    cx<double> inc = mk(0.0, 0.0), err = mk(0.0, 0.0);
+    cx<double> inc = mk(0.0, 0.0), err = fa.E ? fa.E[idx] : mk(0.0, 0.0);
 #pragma unroll
     for (int j = 0; j < 6; ++j) {
       if (j >= fa.s) break;
       inc = inc + (fa.bI[j] * fi[j] + fa.bE[j] * fe[j]);
       err = err + (fa.dI[j] * fi[j] + fa.dE[j] * fe[j]);
     }
-    const cx<double> yn = y0 + inc;
+    const cx<double> yn = (fa.U ? fa.U[idx] : y0) + inc;
     fa.ynew[idx] = yn;
     if (!isfinite(yn.re) || !isfinite(yn.im)) bad += 1.0;
     if (fa.want_err) {

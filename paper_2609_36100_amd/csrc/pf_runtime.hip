@@ -394,9 +394,14 @@ static pf_status run_stage(pf_ctx* c, const StageArgs<TE>& sa, bool need_rhs, cx
   const double nv = (double)c->g.nz * c->g.ny * c->g.nxh;
   const double fT = nv * sizeof(cx<T>), fE = nv * sizeof(cx<TE>), f64 = nv * sizeof(cx<double>);
   double b_stage = 4 * f64;  // state read
-  for (int j = 0; j < sa.nprev; ++j)
-    b_stage += 4 * ((sa.cE[j] != 0.0 ? fE : 0.0) + ((sa.cI[j] != 0.0 && !(j == 0 && sa.fi0_from_y)) ? f64 : 0.0));
+  const bool fold = sa.U_out != nullptr;
+  for (int j = 0; j < sa.nprev; ++j) {
+    const bool useE = sa.cE[j] != 0.0 || (fold && (sa.uE[j] != 0.0 || sa.eE[j] != 0.0));
+    const bool useI = sa.cI[j] != 0.0 || (fold && (sa.uI[j] != 0.0 || sa.eI[j] != 0.0));
+    b_stage += 4 * ((useE ? fE : 0.0) + ((useI && !(j == 0 && sa.fi0_from_y)) ? f64 : 0.0));
+  }
   b_stage += (sa.FI_out ? 4 * f64 : 0.0) + (sa.FEc_out ? fE : 0.0) + (need_rhs ? 4 * fT : 0.0);
+  b_stage += fold ? 2 * 4 * f64 : 0.0;  // U and E
   prof_begin(c);
   if (!launch_stage_invz<T, TE>(c, sa, T1, need_rhs ? 1 : 0)) return PF_ERR_UNSUPPORTED_SIZE;
   prof_end(c, KC_STAGE, b_stage);
@@ -451,6 +456,19 @@ static pf_status stages_and_finalize(pf_ctx* c, double dt, int* n_rhs) {
     sa.gdt = dt * tb.AI[i][i];
     sa.fi0_from_y = c->fi0_derived ? 1 : 0;
     sa.FI_out = (c->fi_need[i] && !(i == 0 && c->fi0_derived)) ? c->FI[i] : nullptr;
+    if (c->fold_last && i == tb.s - 1) {
+      sa.FI_out = nullptr;  // this stage's F^I enters U and E only
+      sa.U_out = c->FI[i];
+      sa.E_out = c->FI[0];
+      for (int j = 0; j < i; ++j) {
+        sa.uE[j] = c->fe_need[j] ? dt * tb.bE[j] : 0.0;
+        sa.uI[j] = c->fi_need[j] ? dt * tb.bI[j] : 0.0;
+        sa.eE[j] = c->fe_need[j] ? dt * (tb.bE[j] - tb.bt[j]) : 0.0;
+        sa.eI[j] = c->fi_need[j] ? dt * (tb.bI[j] - tb.bt[j]) : 0.0;
+      }
+      sa.uIs = dt * tb.bI[i];
+      sa.eIs = dt * (tb.bI[i] - tb.bt[i]);
+    }
     const bool need_rhs = c->fe_need[i];
     sa.FEc_out = (need_rhs && c->mk.fEa != 0.0) ? (cx<TE>*)c->FE[i] : nullptr;
     pf_status s = run_stage<T, TE>(c, sa, need_rhs, (cx<TE>*)c->FE[i]);
@@ -472,12 +490,22 @@ static pf_status stages_and_finalize(pf_ctx* c, double dt, int* n_rhs) {
   fa.s = tb.s;
   fa.want_err = tb.has_emb;
   fa.fi0_from_y = c->fi0_derived ? 1 : 0;
+  if (c->fold_last) {  // everything but the last stage's F^E is in U and E
+    const int l = tb.s - 1;
+    for (int j = 0; j < tb.s; ++j) fa.bE[j] = fa.bI[j] = fa.dE[j] = fa.dI[j] = 0.0;
+    fa.bE[l] = dt * tb.bE[l];
+    fa.dE[l] = dt * (tb.bE[l] - tb.bt[l]);
+    fa.fi0_from_y = 0;
+    fa.U = c->FI[l];
+    fa.E = c->FI[0];
+  }
   fa.rtol = c->p.rtol;
   fa.atol = c->p.atol;
   fa.sc = 1.0 / std::sqrt((double)c->g.nx * c->g.ny * c->g.nz);
   fa.partial = c->partial;
   // y read + ynew write (4 complex FP64 fields each)
   double b_fin = 2.0 * 4 * c->g.nz * (double)c->g.ny * c->g.nxh * sizeof(cx<double>);
+  if (fa.U) b_fin += 2.0 * 4 * c->g.nz * (double)c->g.ny * c->g.nxh * sizeof(cx<double>);  // U and E
   for (int j = 0; j < tb.s; ++j) {
     const double nv = 4.0 * c->g.nz * (double)c->g.ny * c->g.nxh;
     if ((fa.bI[j] != 0.0 || fa.dI[j] != 0.0) && !(j == 0 && fa.fi0_from_y)) b_fin += nv * sizeof(cx<double>);
@@ -564,6 +592,10 @@ void ctx_setup(pf_ctx* c, const pf_params* p, hipStream_t stream) {
   }
   // explicit first stage: its value is the state, F^I_1 = L y is formed where used
   c->fi0_derived = c->tab.AI[0][0] == 0.0 && c->fi_need[0];
+  {
+    const int l = c->tab.s - 1;
+    c->fold_last = c->tab.has_emb && c->fi0_derived && l >= 1 && c->fe_need[l] && c->fi_need[l];
+  }
   std::memset(&c->st, 0, sizeof(c->st));
   c->dt_next = p->dt0;
   c->st.dt_min_seen = 1e300;
