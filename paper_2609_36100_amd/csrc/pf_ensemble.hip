@@ -70,12 +70,17 @@ struct StageCoef {
   double aE[6], aI[6], aii;
   int fi_out, fe_need;
   int fi0_from_y;  // F^I_1 = L(k) y formed in place (explicit first stage)
+  // last stage: update / error sums into FI[stage] (U) and FI[0] (E), with
+  // weights b and b - b~ (times each member's dt), as in the single grid
+  int fold;
+  double uE[6], uI[6], eE[6], eI[6], uIs, eIs;
 };
 
 struct FinCoef {
   double bE[6], bI[6], dE[6], dI[6];
   int s, want_err;
   int fi0_from_y;  // as in StageCoef
+  int fold;        // y_new = U + ..., error = E + ... (U in FI[s-1], E in FI[0])
 };
 
 // kernel kinds with their own work list and work-group size
@@ -141,8 +146,17 @@ __global__ void __launch_bounds__(EB) kb_stage(const EMemb<T, TE>* mem, const ES
   sa.gdt = dt * sc.aii;
   sa.FI_out = sc.fi_out ? e.FI[NP] : nullptr;
   sa.fi0_from_y = sc.fi0_from_y;
-  sa.U_out = nullptr;  // the ensemble update reads the stage arrays itself
-  sa.E_out = nullptr;
+  sa.U_out = sc.fold ? e.FI[NP] : nullptr;
+  sa.E_out = sc.fold ? e.FI[0] : nullptr;
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
+    sa.uE[j] = dt * sc.uE[j];
+    sa.uI[j] = dt * sc.uI[j];
+    sa.eE[j] = dt * sc.eE[j];
+    sa.eI[j] = dt * sc.eI[j];
+  }
+  sa.uIs = dt * sc.uIs;
+  sa.eIs = dt * sc.eIs;
   sa.FEc_out = e.mk.fEa != 0.0 ? e.FE[NP] : nullptr;
   switch (e.g.nz) {
 #define PF_C(N)                                                                                       \
@@ -289,14 +303,14 @@ __global__ void __launch_bounds__(256) kb_finalize(const EMemb<T, TE>* mem, cons
       const double k2 = kx * kx + ky * ky + kz * kz;
       fi[0] = lsym(e.mk, f, k2) * y0;
     }
-    cx<double> inc = mk(0.0, 0.0), err = mk(0.0, 0.0);
+    cx<double> inc = mk(0.0, 0.0), err = fc.fold ? e.FI[0][idx] : mk(0.0, 0.0);
 #pragma unroll
     for (int j = 0; j < 6; ++j) {
       if (j >= fc.s) break;
       inc = inc + ((dt * fc.bI[j]) * fi[j] + (dt * fc.bE[j]) * fe[j]);
       err = err + ((dt * fc.dI[j]) * fi[j] + (dt * fc.dE[j]) * fe[j]);
     }
-    const cx<double> yn = y0 + inc;
+    const cx<double> yn = (fc.fold ? e.FI[fc.s - 1][idx] : y0) + inc;
     ynew[idx] = yn;
     if (!isfinite(yn.re) || !isfinite(yn.im)) bad += 1.0;
     if (fc.want_err) {
@@ -402,6 +416,7 @@ struct pf_ens {
   ArkTable tab;
   bool fe_need[6], fi_need[6];
   bool fi0_derived = false;  // explicit first stage: F^I_1 = L y, never stored
+  bool fold_last = false;    // last stage forms the update and error sums
   hipGraphExec_t exec = nullptr;
   hipGraph_t graph = nullptr;
   std::map<int, std::pair<cx<double>*, cx<double>*>> tw64;  // N -> (w_N, w_{N/2})
@@ -491,6 +506,19 @@ static void launch_kind(pf_ens* E, int kind, int stage) {
         sc.aii = E->tab.AI[stage][stage];
         sc.fi0_from_y = E->fi0_derived ? 1 : 0;
         sc.fi_out = (E->fi_need[stage] && !(stage == 0 && E->fi0_derived)) ? 1 : 0;
+        if (E->fold_last && stage == E->tab.s - 1) {
+          const ArkTable& tb = E->tab;
+          sc.fold = 1;
+          sc.fi_out = 0;
+          for (int j = 0; j < stage; ++j) {
+            sc.uE[j] = E->fe_need[j] ? tb.bE[j] : 0.0;
+            sc.uI[j] = E->fi_need[j] ? tb.bI[j] : 0.0;
+            sc.eE[j] = E->fe_need[j] ? tb.bE[j] - tb.bt[j] : 0.0;
+            sc.eI[j] = E->fi_need[j] ? tb.bI[j] - tb.bt[j] : 0.0;
+          }
+          sc.uIs = tb.bI[stage];
+          sc.eIs = tb.bI[stage] - tb.bt[stage];
+        }
         switch (stage) {
           case 0: kb_stage<T, TE, EB, 0><<<nb, EB, 0, s>>>(mem, E->st_dev, st, E->M, sc); break;
           case 1: kb_stage<T, TE, EB, 1><<<nb, EB, 0, s>>>(mem, E->st_dev, st, E->M, sc); break;
@@ -554,6 +582,14 @@ static void enqueue_step(pf_ens* E) {
   fc.s = tb.s;
   fc.want_err = tb.has_emb;
   fc.fi0_from_y = E->fi0_derived ? 1 : 0;
+  if (E->fold_last) {
+    const int l = tb.s - 1;
+    for (int j = 0; j < tb.s; ++j) fc.bE[j] = fc.bI[j] = fc.dE[j] = fc.dI[j] = 0.0;
+    fc.bE[l] = tb.bE[l];
+    fc.dE[l] = tb.bE[l] - tb.bt[l];
+    fc.fi0_from_y = 0;
+    fc.fold = 1;
+  }
   const EMemb<T, TE>* mem = (const EMemb<T, TE>*)E->mem_dev;
   kb_finalize<T, TE><<<E->nfin, 256, 0, E->stream>>>(mem, E->st_dev, E->fin_start, E->M, fc, E->partial);
   kb_control<T, TE><<<E->M, 256, 0, E->stream>>>(mem, E->st_dev, E->fin_start, E->partial, tb.emb_order,
@@ -648,6 +684,8 @@ pf_status pf_ensemble_init(int32_t n, const pf_params* per_member, void* stream,
     E->fi_need[i] = fi_needed(E->tab, i);
   }
   E->fi0_derived = E->tab.AI[0][0] == 0.0 && E->fi_need[0];
+  E->fold_last = E->tab.has_emb && E->fi0_derived && E->tab.s >= 2 && E->fe_need[E->tab.s - 1] &&
+                 E->fi_need[E->tab.s - 1];
   pf_status s = PF_OK;
   // per-size twiddle tables
   for (int m = 0; m < n && s == PF_OK; ++m) {
