@@ -73,11 +73,15 @@ def kernel_table(rep):
     return out
 
 
-def run_solver(torch, n, c, eta, precision, steps, warmup, dt):
+def run_solver(torch, n, c, eta, precision, steps, warmup, dt, variants=None):
     from paper_2609_36100_amd import Solver
     s = Solver(n, None, method="ark436l", precision=precision, dt0=dt)
     s.set_state(c, eta)
     tuning = s.autotune(3)          # tile plans, chosen before the timed region
+    if variants:                    # fixed plans (e.g. to repeat a profiled run's choice)
+        for k, v in enumerate(variants):
+            s.set_tuning(k, v)
+        tuning = s.tuning()
     log("%s tile plans: %s" % (precision, {k: (v["variant"], [round(x, 3) for x in v["ms"]]) for k, v in tuning.items()}))
     for _ in range(warmup):
         acc, _, _ = s.step(dt)
@@ -399,6 +403,9 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=512)
+    ap.add_argument("--variants", default=None,
+                    help="throughput: fixed tile variants after autotuning, 'a,b,c,d' (FP64) or "
+                         "'a,b,c,d/e,f,g,h' (FP64/mixed) for colfft, stage_invz, zpass_elastic, zpass_fwd_ac")
     ap.add_argument("--dt", type=float, default=0.1)
     ap.add_argument("--skip-mixed", action="store_true")
     ap.add_argument("--skip-fft", action="store_true")
@@ -510,12 +517,17 @@ def main():
     del c, eta
 
     log("FP64 run: %d warmup + %d timed ARK4 steps" % (args.warmup, args.steps))
-    r64 = run_solver(torch, n, ct, et, "fp64", args.steps, args.warmup, args.dt)
+    var64 = var32 = None
+    if args.variants:
+        parts = [[int(x) for x in q.split(",")] for q in args.variants.split("/")]
+        var64 = parts[0]
+        var32 = parts[1] if len(parts) > 1 else None
+    r64 = run_solver(torch, n, ct, et, "fp64", args.steps, args.warmup, args.dt, var64)
     log("FP64 %.1f Mpts*stages/s, %.1f ms/step" % (r64["value"], r64["ms_per_step"]))
     mixed = None
     if not args.skip_mixed:
         log("mixed run")
-        rm = run_solver(torch, n, ct, et, "mixed", args.steps, args.warmup, args.dt)
+        rm = run_solver(torch, n, ct, et, "mixed", args.steps, args.warmup, args.dt, var32)
         log("mixed %.1f Mpts*stages/s, %.1f ms/step" % (rm["value"], rm["ms_per_step"]))
         mixed = dict(value=round(rm["value"], 2), ms_per_step=round(rm["ms_per_step"], 3),
                      dtype="f32 FFT/pointwise/elastic, f64 stage sums and error", kernels=rm["kernels"],
