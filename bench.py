@@ -352,6 +352,124 @@ def oracle_timing(sizes_rhs=(64, 128, 256), sizes_step=(64, 128), threads=None):
     return out
 
 
+def fno_bench(torch, t_final, runs, val_runs, snapshots, epochs, train_s, members, dt_ref_t, lr, ensemble=True):
+    """Learned surrogate: plain-solver training data at 128^3, GPU training, held-out
+    validation, then the 128^3 members of the uneven ensemble advanced to t_final
+    with the checked surrogate against plain adaptive ARK4 (the gain test)."""
+    import numpy as np
+    import pfinputs
+    from paper_2609_36100_amd import Solver, rel_l2
+    from paper_2609_36100_amd import surrogate as sg
+    n = 128
+    out = dict(n=n, width=32, modes=12, layers=4, hidden=128)
+    t0 = time.perf_counter()
+    dt_ref, _ = sg.reference_dt(n, 0, dt_ref_t)
+    delta = 10.0 * dt_ref
+    out.update(dt_ref=dt_ref, delta=delta, dt_ref_window=dt_ref_t)
+    log("dt_ref %.5f (mean accepted ARK4 step over [0, %g] of run 0), delta %.5f" % (dt_ref, dt_ref_t, delta))
+    snaps, steps = sg.generate_snapshots(n, runs + val_runs, snapshots, delta, log=log)
+    out["data"] = dict(runs=runs, val_runs=val_runs, snapshots=snapshots, pairs=runs * snapshots,
+                       plain_steps=steps, wall_s=round(time.perf_counter() - t0, 1))
+    scale = sg.increment_scale(snaps, runs)
+    norm = sg.state_norm(snaps, runs)
+    out["scale"] = [float("%.4e" % v) for v in scale]
+    out["input_norm"] = dict(mean=[float("%.4e" % v) for v in norm[0]], std=[float("%.4e" % v) for v in norm[1]])
+    f = sg.make_fno(n, 32, 12, 4, 128, seed=0, scale=scale, norm=norm)
+    val = list(range(runs, runs + val_runs))
+    e0, keep, inc0 = sg.validate(f, snaps, val)
+    t1 = time.perf_counter()
+    hist = sg.train(f, snaps, runs, epochs=epochs, lr=lr, batch=4, seed=0, log=log, time_limit=train_s)
+    out["train"] = dict(epochs=len(hist), loss=[float("%.4e" % v) for v in hist],
+                        wall_s=round(time.perf_counter() - t1, 1))
+    e1, _, inc1 = sg.validate(f, snaps, val)
+    out["validation_rel_l2_c"] = dict(untrained_mean=float("%.3e" % e0.mean()), trained_mean=float("%.3e" % e1.mean()),
+                                      trained_max=float("%.3e" % e1.max()), no_change_mean=float("%.3e" % keep.mean()),
+                                      frac_below_tol=float("%.3f" % (e1 <= 1e-3).mean()),
+                                      increment_rel_err=[float("%.3f" % v) for v in inc1],
+                                      increment_rel_err_untrained=[float("%.3f" % v) for v in inc0])
+    log("validation rel-L2(c): trained %.3e (max %.3e), untrained %.3e, no change %.3e"
+        % (e1.mean(), e1.max(), e0.mean(), keep.mean()))
+    del snaps
+    torch.cuda.empty_cache()
+    # gain test on the ensemble's 128^3 members
+    mem = [m for m in pfinputs.ensemble_members(64) if m["n"] == n][:members]
+    # default horizon: the training window (snapshots x delta)
+    n_adv = int(round(t_final / delta)) if t_final > 0 else snapshots
+    t_end = n_adv * delta
+    kw = dict(method="ark436l", adaptive=True, dt0=0.01, rtol=1e-6, atol=1e-9)
+    res = []
+    tot_plain = tot_sur = 0.0
+    for i, m in enumerate(mem):
+        with Solver(n, None, **kw) as s:
+            s.set_state(m["c"], m["eta"])
+            torch.cuda.synchronize()
+            ta = time.perf_counter()
+            st = s.advance(t_end)
+            torch.cuda.synchronize()
+            w_plain = time.perf_counter() - ta
+            u_plain = s.get_state_device().clone()
+            vf_plain = s.diagnostics()["vf"]
+            s.set_state(m["c"], m["eta"])
+            u = s.get_state_device().clone()
+            s.set_dt(0.01)
+            torch.cuda.synchronize()
+            ta = time.perf_counter()
+            fs = sg.checked_advance(f, s, u, t_end, delta, check_every=5, tol=1e-3)
+            torch.cuda.synchronize()
+            w_sur = time.perf_counter() - ta
+            s.set_state_device(u)
+            vf_sur = s.diagnostics()["vf"]
+        with Solver(n, None, method="ark436l", adaptive=True, dt0=0.01, rtol=1e-8, atol=1e-11) as r:
+            r.set_state(m["c"], m["eta"])
+            r.advance(t_end)
+            u_ref = r.get_state_device()
+            vf_ref = r.diagnostics()["vf"]
+        tot_plain += w_plain
+        tot_sur += w_sur
+        d = fs.as_dict()
+        res.append(dict(member=m["member"], plain_s=round(w_plain, 3), plain_steps=st["steps"],
+                        surrogate_s=round(w_sur, 3), surrogate=d["surrogate"], checks=d["checks"],
+                        fallbacks=d["fallbacks"], plain_advances=d["plain"],
+                        check_err_max=float("%.3e" % d["err_max"]),
+                        vf_err_plain=float("%.3e" % abs(vf_plain - vf_ref)),
+                        vf_err_surrogate=float("%.3e" % abs(vf_sur - vf_ref)),
+                        c_rel_l2_plain=float("%.3e" % rel_l2(u_plain[0], u_ref[0])),
+                        c_rel_l2_surrogate=float("%.3e" % rel_l2(u[0], u_ref[0]))))
+        log("member %d: plain %.2f s (%d steps), surrogate %.2f s (%d net, %d checks, %d fallbacks), "
+            "vf err %.1e / %.1e" % (m["member"], w_plain, st["steps"], w_sur, d["surrogate"], d["checks"],
+                                    d["fallbacks"], res[-1]["vf_err_plain"], res[-1]["vf_err_surrogate"]))
+    out["gain"] = dict(t_final=t_end, members=len(mem), plain_s=round(tot_plain, 3), surrogate_s=round(tot_sur, 3),
+                       speedup=round(tot_plain / tot_sur, 3) if tot_sur > 0 else None,
+                       vf_err_max_plain=max(r["vf_err_plain"] for r in res),
+                       vf_err_max_surrogate=max(r["vf_err_surrogate"] for r in res),
+                       fallbacks=sum(r["fallbacks"] for r in res), per_member=res)
+    if ensemble:
+        # the whole uneven ensemble: batched plain solver for every member, against batched
+        # plain for the other sizes plus the checked surrogate for the 128^3 members
+        from paper_2609_36100_amd import Ensemble
+        allm = pfinputs.ensemble_members(64)
+        rest = [m for m in allm if m["n"] != n]
+        walls = {}
+        for name, group in (("all_plain", allm), ("other_sizes_plain", rest)):
+            log("ensemble %s (%d members) to t=%g" % (name, len(group), t_end))
+            with Ensemble([dict(n=m["n"], **kw) for m in group]) as E:
+                for i, m in enumerate(group):
+                    E.set_state(i, m["c"], m["eta"])
+                torch.cuda.synchronize()
+                ta = time.perf_counter()
+                E.advance(t_end)
+                torch.cuda.synchronize()
+                walls[name] = time.perf_counter() - ta
+        full128 = sum(1 for m in allm if m["n"] == n)
+        sur_all = tot_sur * full128 / max(len(mem), 1)
+        out["gain"]["ensemble"] = dict(
+            members=len(allm), members_128=full128, all_plain_s=round(walls["all_plain"], 3),
+            other_sizes_plain_s=round(walls["other_sizes_plain"], 3),
+            with_surrogate_s=round(walls["other_sizes_plain"] + sur_all, 3),
+            speedup=round(walls["all_plain"] / (walls["other_sizes_plain"] + sur_all), 3))
+    return out
+
+
 def fno_step_bench(torch, n=128, reps=10):
     """The surrogate's kernels on their own: one training step (forward, loss,
     backward) and one surrogate advance at n^3 (width 32, 12 modes, 4 layers),

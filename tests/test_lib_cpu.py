@@ -138,3 +138,15 @@ def test_plain_c_client_builds_and_reports_missing_device():
     out = subprocess.run([exe, "8", "/tmp/pf_abi_in.bin", "/tmp/pf_abi_out.bin"], capture_output=True, text=True,
                          timeout=120)
     assert out.returncode == 10 and "PF_ERR_HIP" in out.stderr, (out.returncode, out.stderr)
+
+
+def test_every_bench_mode_has_its_driver():
+    """bench.py's modes dispatch to module-level drivers; each must exist (a
+    missing one would only show when that mode runs on a GPU)."""
+    import bench
+    for name in ("run_solver", "fft_bench", "cpu_baseline", "ensemble_bench", "time_to_t_bench",
+                 "orders_bench", "oracle_timing", "fno_bench", "fno_step_bench", "measured_traffic"):
+        assert callable(getattr(bench, name, None)), name
+    src = open(os.path.join(ROOT, "bench.py")).read()
+    for mode in ("ensemble", "time_to_t", "fno", "fno_step", "orders", "oracle_timing"):
+        assert 'args.mode == "%s"' % mode in src, mode
