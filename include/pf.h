@@ -248,7 +248,9 @@ pf_status pf_ensemble_diagnostics(pf_ens* ens, int32_t m, double* mass, double* 
  * max_steps ran out first. */
 pf_status pf_ensemble_advance(pf_ens* ens, const double* t_final, int32_t max_steps, pf_stats* per_member);
 /* Autotuner: for each pass kind, time work-groups of 128 and 256 threads on
- * the whole ensemble and keep the faster (the step graph is re-captured). */
+ * the whole ensemble and keep the faster (the step graph is re-captured).
+ * The stage kind is timed over all stages of one step; ms128 / ms256 from
+ * pf_ensemble_tuning_get are per timed launch sequence. */
 pf_status pf_ensemble_autotune(pf_ens* ens, int32_t reps);
 int32_t pf_ensemble_tuning_kinds(void);
 const char* pf_ensemble_tuning_name(int32_t kind);

@@ -73,7 +73,7 @@ struct StageCoef {
   // last stage: update / error sums into FI[stage] (U) and FI[0] (E), with
   // weights b and b - b~ (times each member's dt), as in the single grid
   int fold;
-  double uE[6], uI[6], eE[6], eI[6], uIs, eIs;
+  double ub[6], eb[6], ubs, ebs;
 };
 
 struct FinCoef {
@@ -150,13 +150,12 @@ __global__ void __launch_bounds__(EB) kb_stage(const EMemb<T, TE>* mem, const ES
   sa.E_out = sc.fold ? e.FI[0] : nullptr;
 #pragma unroll
   for (int j = 0; j < 6; ++j) {
-    sa.uE[j] = dt * sc.uE[j];
-    sa.uI[j] = dt * sc.uI[j];
-    sa.eE[j] = dt * sc.eE[j];
-    sa.eI[j] = dt * sc.eI[j];
+    sa.ub[j] = sc.ub[j];
+    sa.eb[j] = sc.eb[j];
   }
-  sa.uIs = dt * sc.uIs;
-  sa.eIs = dt * sc.eIs;
+  sa.ubs = sc.ubs;
+  sa.ebs = sc.ebs;
+  sa.fdt = dt;
   sa.FEc_out = e.mk.fEa != 0.0 ? e.FE[NP] : nullptr;
   switch (e.g.nz) {
 #define PF_C(N)                                                                                       \
@@ -510,14 +509,12 @@ static void launch_kind(pf_ens* E, int kind, int stage) {
           const ArkTable& tb = E->tab;
           sc.fold = 1;
           sc.fi_out = 0;
-          for (int j = 0; j < stage; ++j) {
-            sc.uE[j] = E->fe_need[j] ? tb.bE[j] : 0.0;
-            sc.uI[j] = E->fi_need[j] ? tb.bI[j] : 0.0;
-            sc.eE[j] = E->fe_need[j] ? tb.bE[j] - tb.bt[j] : 0.0;
-            sc.eI[j] = E->fi_need[j] ? tb.bI[j] - tb.bt[j] : 0.0;
+          for (int j = 0; j < stage; ++j) {  // b^E = b^I here (fold_last)
+            sc.ub[j] = tb.bI[j];
+            sc.eb[j] = tb.bI[j] - tb.bt[j];
           }
-          sc.uIs = tb.bI[stage];
-          sc.eIs = tb.bI[stage] - tb.bt[stage];
+          sc.ubs = tb.bI[stage];
+          sc.ebs = tb.bI[stage] - tb.bt[stage];
         }
         switch (stage) {
           case 0: kb_stage<T, TE, EB, 0><<<nb, EB, 0, s>>>(mem, E->st_dev, st, E->M, sc); break;
@@ -684,8 +681,12 @@ pf_status pf_ensemble_init(int32_t n, const pf_params* per_member, void* stream,
     E->fi_need[i] = fi_needed(E->tab, i);
   }
   E->fi0_derived = E->tab.AI[0][0] == 0.0 && E->fi_need[0];
-  E->fold_last = E->tab.has_emb && E->fi0_derived && E->tab.s >= 2 && E->fe_need[E->tab.s - 1] &&
-                 E->fi_need[E->tab.s - 1];
+  {
+    bool same_b = true;
+    for (int j = 0; j < E->tab.s; ++j) same_b = same_b && E->tab.bE[j] == E->tab.bI[j];
+    E->fold_last = E->tab.has_emb && same_b && E->fi0_derived && E->tab.s >= 2 && E->fe_need[E->tab.s - 1] &&
+                   E->fi_need[E->tab.s - 1];
+  }
   pf_status s = PF_OK;
   // per-size twiddle tables
   for (int m = 0; m < n && s == PF_OK; ++m) {
@@ -922,12 +923,18 @@ pf_status pf_ensemble_autotune(pf_ens* E, int32_t reps) {
     int bv = 1;
     for (int v = 0; v < 2; ++v) {
       E->var[k] = v;
-      const int stage = (k == EK_STAGE) ? 3 : (k == EK_YFFT4 || k == EK_YFFT3) ? 1 : 0;
+      const int stage = (k == EK_YFFT4 || k == EK_YFFT3) ? 1 : 0;
+      // the stage kernel differs per stage (number of previous stages, the
+      // last stage's update sums): time the whole sequence of a step
+      const int s0 = (k == EK_STAGE) ? 0 : stage;
+      const int s1 = (k == EK_STAGE) ? E->tab.s : stage + 1;
       auto run = [&]() {
-        if (E->mixed)
-          launch_kind<float, float>(E, k, stage);
-        else
-          launch_kind<double, double>(E, k, stage);
+        for (int st = s0; st < s1; ++st) {
+          if (E->mixed)
+            launch_kind<float, float>(E, k, st);
+          else
+            launch_kind<double, double>(E, k, st);
+        }
       };
       run();
       PF_HIP(hipEventRecord(e0, E->stream));

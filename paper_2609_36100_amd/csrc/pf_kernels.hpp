@@ -284,17 +284,21 @@ struct StageArgs {
   // first stage (A^I_11 = 0) the first stage value is the state itself, so
   // F^I_1 = L y exactly and the array is never stored.
   int fi0_from_y;
-  // Last stage of an embedded method only (U_out non-null): the update and
+  // Last stage of an embedded method whose explicit and implicit weights
+  // agree (b^E = b^I = b; one embedded b~), U_out non-null: the update and
   // error sums of the step (Eqs. ARK_method, ARK_embedding) over every term
   // but the last stage's explicit derivative are formed here, from values
   // this kernel loads anyway plus the last stage's own F^I (never stored):
-  //   U = y + sum_{j<i} (uE_j F^E_j + uI_j F^I_j) + uIs F^I_i,
-  //   E =     sum_{j<i} (eE_j F^E_j + eI_j F^I_j) + eIs F^I_i,
-  // with u = dt b and e = dt (b - b~).  The update then reads y, U, E, F^E_i.
+  //   U = y + dt (sum_{j<i} ub_j (F^E_j + F^I_j) + ub_i F^I_i),
+  //   E =     dt (sum_{j<i} eb_j (F^E_j + F^I_j) + eb_i F^I_i),
+  // with ub = b and eb = b - b~ (zero where a stage array is not kept).  The
+  // update then reads y, U, E and F^E_i.  One weight set for both parts keeps
+  // the uniform operands few (they live in scalar registers).
   cx<double>* U_out;
   cx<double>* E_out;
-  double uE[6], uI[6], eE[6], eI[6];
-  double uIs, eIs;
+  double ub[6], eb[6];  // indices < i; ub[i], eb[i] in ubs, ebs
+  double ubs, ebs;
+  double fdt;           // dt
 };
 
 // Stage combination for one element (Eq. ARK_stage restricted to the
@@ -307,8 +311,9 @@ __device__ inline cx<double> stage_value(const StageArgs<TE>& sa, long long idx,
   cx<double> fe[NP > 0 ? NP : 1], fi[NP > 0 ? NP : 1];
 #pragma unroll
   for (int j = 0; j < NP; ++j) {
-    const bool useE = sa.cE[j] != 0.0 || (fold && (sa.uE[j] != 0.0 || sa.eE[j] != 0.0));
-    const bool useI = sa.cI[j] != 0.0 || (fold && (sa.uI[j] != 0.0 || sa.eI[j] != 0.0));
+    const bool useF = fold && (sa.ub[j] != 0.0 || sa.eb[j] != 0.0);
+    const bool useE = sa.cE[j] != 0.0 || useF;
+    const bool useI = sa.cI[j] != 0.0 || useF;
     fe[j] = useE ? to_d(sa.FE[j][idx]) : mk(0.0, 0.0);
     if (j == 0 && sa.fi0_from_y)
       fi[0] = L * y0;
@@ -323,14 +328,15 @@ __device__ inline cx<double> stage_value(const StageArgs<TE>& sa, long long idx,
   if (FIo) FIo[idx] = fin;
   if (f == 0 && FEo) FEo[idx] = to_t<TE>((-fea_k2) * zz);
   if (fold) {
-    cx<double> u = y0, e = mk(0.0, 0.0);
+    cx<double> u = sa.ubs * fin, e = sa.ebs * fin;
 #pragma unroll
     for (int j = 0; j < NP; ++j) {
-      u = u + (sa.uE[j] * fe[j] + sa.uI[j] * fi[j]);
-      e = e + (sa.eE[j] * fe[j] + sa.eI[j] * fi[j]);
+      const cx<double> fj = fe[j] + fi[j];
+      u = u + sa.ub[j] * fj;
+      e = e + sa.eb[j] * fj;
     }
-    sa.U_out[idx] = u + sa.uIs * fin;
-    sa.E_out[idx] = e + sa.eIs * fin;
+    sa.U_out[idx] = y0 + sa.fdt * u;
+    sa.E_out[idx] = sa.fdt * e;
   }
   return zz;
 }

@@ -396,8 +396,9 @@ static pf_status run_stage(pf_ctx* c, const StageArgs<TE>& sa, bool need_rhs, cx
   double b_stage = 4 * f64;  // state read
   const bool fold = sa.U_out != nullptr;
   for (int j = 0; j < sa.nprev; ++j) {
-    const bool useE = sa.cE[j] != 0.0 || (fold && (sa.uE[j] != 0.0 || sa.eE[j] != 0.0));
-    const bool useI = sa.cI[j] != 0.0 || (fold && (sa.uI[j] != 0.0 || sa.eI[j] != 0.0));
+    const bool useF = fold && (sa.ub[j] != 0.0 || sa.eb[j] != 0.0);
+    const bool useE = sa.cE[j] != 0.0 || useF;
+    const bool useI = sa.cI[j] != 0.0 || useF;
     b_stage += 4 * ((useE ? fE : 0.0) + ((useI && !(j == 0 && sa.fi0_from_y)) ? f64 : 0.0));
   }
   b_stage += (sa.FI_out ? 4 * f64 : 0.0) + (sa.FEc_out ? fE : 0.0) + (need_rhs ? 4 * fT : 0.0);
@@ -460,14 +461,13 @@ static pf_status stages_and_finalize(pf_ctx* c, double dt, int* n_rhs) {
       sa.FI_out = nullptr;  // this stage's F^I enters U and E only
       sa.U_out = c->FI[i];
       sa.E_out = c->FI[0];
-      for (int j = 0; j < i; ++j) {
-        sa.uE[j] = c->fe_need[j] ? dt * tb.bE[j] : 0.0;
-        sa.uI[j] = c->fi_need[j] ? dt * tb.bI[j] : 0.0;
-        sa.eE[j] = c->fe_need[j] ? dt * (tb.bE[j] - tb.bt[j]) : 0.0;
-        sa.eI[j] = c->fi_need[j] ? dt * (tb.bI[j] - tb.bt[j]) : 0.0;
+      for (int j = 0; j < i; ++j) {  // b^E = b^I here (fold_last); zero weights read nothing
+        sa.ub[j] = tb.bI[j];
+        sa.eb[j] = tb.bI[j] - tb.bt[j];
       }
-      sa.uIs = dt * tb.bI[i];
-      sa.eIs = dt * (tb.bI[i] - tb.bt[i]);
+      sa.ubs = tb.bI[i];
+      sa.ebs = tb.bI[i] - tb.bt[i];
+      sa.fdt = dt;
     }
     const bool need_rhs = c->fe_need[i];
     sa.FEc_out = (need_rhs && c->mk.fEa != 0.0) ? (cx<TE>*)c->FE[i] : nullptr;
@@ -594,7 +594,9 @@ void ctx_setup(pf_ctx* c, const pf_params* p, hipStream_t stream) {
   c->fi0_derived = c->tab.AI[0][0] == 0.0 && c->fi_need[0];
   {
     const int l = c->tab.s - 1;
-    c->fold_last = c->tab.has_emb && c->fi0_derived && l >= 1 && c->fe_need[l] && c->fi_need[l];
+    bool same_b = true;  // one weight set for the explicit and implicit parts
+    for (int j = 0; j < c->tab.s; ++j) same_b = same_b && c->tab.bE[j] == c->tab.bI[j];
+    c->fold_last = c->tab.has_emb && same_b && c->fi0_derived && l >= 1 && c->fe_need[l] && c->fi_need[l];
   }
   std::memset(&c->st, 0, sizeof(c->st));
   c->dt_next = p->dt0;
