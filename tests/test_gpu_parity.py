@@ -416,26 +416,31 @@ def test_ark4_step_at_256_adaptive_workload_matches_oracle(torch, params):
     assert abs(err - err_ref) <= 1e-8 * err_ref, (err, err_ref)
 
 
-@pytest.fixture(scope="module")
-def linear512(params):
-    """Oracle side of the 512^3 linear-subproblem step (computed once)."""
-    n, dt = 512, 0.1
-    rng = np.random.default_rng(31)
-    c = 0.16 + 0.01 * rng.standard_normal((1, n, n, n))
-    yc = osp.rfft3(c)
-    del c
-    m = om.Model((n, n, n), params)
-    L = m.implicit_symbol()[0:1].copy()
-    y_new, lte, _ = oark.ark_step(yc, dt, oark.ark436l2sa(), lambda z: 0.0, L)
-    del L
-    # the error vector has 4 N^3 entries, three fields of them zero
-    err_ref = oark.wrms_kspace(lte, yc, 1e-6, 1e-9, m.mult, m.N3) / 2.0
-    return n, dt, yc, y_new[0], err_ref
+_LINEAR = {}
 
 
-@pytest.mark.parametrize("precision", ["fp64", "mixed"])
-def test_ark4_step_at_512_on_the_linear_subproblem(torch, params, linear512, precision):
-    """A whole ARK4(3)6L step at 512^3 in the bench's launch configuration
+def _linear_step(params, n, dt=0.1):
+    """Oracle side of the full-size linear-subproblem step (computed once per n)."""
+    if n not in _LINEAR:
+        _LINEAR.clear()     # one grid's arrays at a time
+        rng = np.random.default_rng(31)
+        c = 0.16 + 0.01 * rng.standard_normal((1, n, n, n))
+        yc = osp.rfft3(c)
+        del c
+        m = om.Model((n, n, n), params)
+        L = m.implicit_symbol()[0:1].copy()
+        y_new, lte, _ = oark.ark_step(yc, dt, oark.ark436l2sa(), lambda z: 0.0, L)
+        del L
+        # the error vector has 4 N^3 entries, three fields of them zero
+        err_ref = oark.wrms_kspace(lte, yc, 1e-6, 1e-9, m.mult, m.N3) / 2.0
+        _LINEAR[n] = (dt, yc, y_new[0], err_ref)
+    return _LINEAR[n]
+
+
+@pytest.mark.parametrize("n,precision", [(512, "fp64"), (512, "mixed"), (504, "fp64")])
+def test_ark4_step_at_full_size_on_the_linear_subproblem(torch, params, n, precision):
+    """A whole ARK4(3)6L step at 512^3 (and at the paper's 504^3, radix-6/7
+    lines) in the bench's launch configuration
     (tuned tile plans): every stage combination, the implicit solves, the
     first-stage F^I formed from the state, the update and error sums of the
     last stage and the update kernel, against the oracle's integrator.  With
@@ -445,8 +450,8 @@ def test_ark4_step_at_512_on_the_linear_subproblem(torch, params, linear512, pre
     y' = L(k) y mode by mode: the oracle's ark_step with a zero explicit part
     gives the state and the error.  The eta fields must stay exactly zero and
     the mass mode bitwise unchanged; the stage sums are FP64 in both forms."""
-    _say("ark4 step 512^3, linear subproblem", precision)
-    n, dt, yc, y_new, err_ref = linear512
+    _say("ark4 step, linear subproblem", n, precision)
+    dt, yc, y_new, err_ref = _linear_step(params, n)
     with _solver(n, params, method="ark436l", dt0=dt, precision=precision) as s:
         t = s.kspace_empty(4)
         t.zero_()
