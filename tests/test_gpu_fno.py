@@ -70,6 +70,40 @@ def test_fno_forward_and_gradients_match_oracle(n, w, m, L, h):
         assert r < BOUND, (k, r)
 
 
+def test_fno_forward_at_128_matches_oracle():
+    """The surrogate's own configuration at its full size (128^3, width 32, 12
+    modes, 4 layers, hidden 128): forward output and loss against the FP64
+    oracle (about a minute of oracle time; the gradients are checked on the
+    smaller grids above with the same kernels)."""
+    import torch
+    from paper_2609_36100_amd import FNO
+    n, w, m, L, h = 128, 32, 12, 4, 128
+    _say("fno forward", n, w, m, L, h)
+    net = of.FNO(n, width=w, modes=m, layers=L, hidden=h)
+    p = net.init_params(seed=17)
+    rng = np.random.default_rng(18)
+    for k in p:
+        if k.startswith("b") or k.startswith("c"):
+            p[k] = 0.1 * rng.standard_normal(p[k].shape)
+    to_bf = lambda a: torch.from_numpy(np.asarray(a, np.float32)).to(torch.bfloat16).to(torch.float64).numpy()
+    p = {k: to_bf(v) for k, v in p.items()}
+    x = to_bf(rng.uniform(0, 1, (n, n, n, 4)))
+    tgt = rng.standard_normal((n, n, n, 4)) * 0.5
+    out = net.forward(p, x)
+    loss, _ = of.mse_loss(out, tgt)
+    with FNO(n, width=w, modes=m, layers=L, hidden=h) as f:
+        f.set_params(_flat(net, p))
+        xt = torch.from_numpy(np.ascontiguousarray(np.moveaxis(x, -1, 0))).float().cuda()
+        yt = xt + torch.from_numpy(np.ascontiguousarray(np.moveaxis(tgt, -1, 0))).float().cuda()
+        gout = f.forward(xt).cpu().numpy().reshape(n, n, n, 4)
+        f.zero_grad()
+        gl = f.grad(xt, yt)
+    rel_out = np.linalg.norm(gout - out) / np.linalg.norm(out)
+    print("forward rel", rel_out, "loss", gl, loss, flush=True)
+    assert rel_out < BOUND
+    assert abs(gl - loss) < BOUND * loss
+
+
 def test_fno_input_normalisation_matches_oracle():
     """The network sees (x - shift) / scale rounded to bf16: the oracle fed that
     input gives the same output and gradients; the loss target stays (y - x)."""
