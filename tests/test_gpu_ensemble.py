@@ -100,6 +100,33 @@ def test_adaptive_ensemble_matches_single_runs(torch, params):
             assert _rel(g, g_ref) < TOL, (m, _rel(g, g_ref))
 
 
+def test_full_64_member_workload_matches_single_runs(torch, params):
+    """The ensemble workload at its full size (64 seeded members of sizes 48,
+    64, 96 and 128, adaptive ARK4(3)6L, tuned block sizes) over the first
+    stretch of the run (t = 0.3, every member dissolving its sharp nuclei):
+    each member's accepted and rejected steps and state against the same
+    member on the single-grid path."""
+    from paper_2609_36100_amd import Ensemble, Solver
+    _say("ensemble 64 members")
+    mem = pfinputs.ensemble_members(64)
+    kw = dict(adaptive=True, dt0=0.01, rtol=1e-6, atol=1e-9)
+    tf = 0.3
+    with Ensemble([dict(n=m["n"], model=params, **kw) for m in mem]) as E:
+        for i, m in enumerate(mem):
+            E.set_state(i, m["c"], m["eta"])
+        E.autotune(1)
+        st = E.advance([tf] * len(mem))
+        for i, m in enumerate(mem):
+            with Solver(m["n"], params, method="ark436l", **kw) as s:
+                s.set_state(m["c"], m["eta"])
+                ref = s.advance(tf)
+                g_ref = s.kspace_to_numpy(s.get_state_hat())
+            g = E.get_state_hat(i)
+            assert abs(st[i]["t"] - tf) < 1e-12
+            assert st[i]["steps"] == ref["steps"] and st[i]["rejects"] == ref["rejects"], (i, st[i], ref)
+            assert _rel(g, g_ref) < TOL, (i, _rel(g, g_ref))
+
+
 def test_mixed_ensemble_error_bound(torch, params):
     from paper_2609_36100_amd import Ensemble
     _say("ensemble mixed")
