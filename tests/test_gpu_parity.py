@@ -342,7 +342,8 @@ def _band_limited_state(n):
     return c, eta
 
 
-def test_rhs_at_512_matches_oracle_on_a_band_limited_state(torch, params):
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_rhs_at_512_matches_oracle_on_a_band_limited_state(torch, params, precision):
     """pf_rhs at the full 512^3 size, with the tile plans the autotuner picks,
     against the oracle on 32^3 with dx scaled by 16 (the same physical box and
     wavevectors): for a band-limited state the unnormalised spectra agree mode
@@ -351,8 +352,11 @@ def test_rhs_at_512_matches_oracle_on_a_band_limited_state(torch, params):
     1e-8 of the explicit derivative (high-k round-off is amplified by k^2 up
     to ~30 in the composition's term; leakage or aliasing would be O(1)).
     The implicit derivative is L(k) times the state mode by mode, so the
-    state's check covers it outside the band."""
-    _say("rhs 512^3 band-limited")
+    state's check covers it outside the band.  In the mixed form the state
+    and F^I stay FP64 (same bounds) and F^E carries FP32 transforms: 1e-4 in
+    and out of the band, the form's stated bound."""
+    _say("rhs 512^3 band-limited", precision)
+    fe_in, fe_out = (1e-10, 1e-8) if precision == "fp64" else (1e-4, 1e-4)
     big, small = 512, 32
     p_small = dict(params)
     p_small["dx"] = params.get("dx", 1.0) * big / small
@@ -361,7 +365,7 @@ def test_rhs_at_512_matches_oracle_on_a_band_limited_state(torch, params):
     Y = om.to_kspace(c, eta)
     FI, FE = m.rhs(Y)
     cb, eb = _band_limited_state(big)
-    with _solver(big, params, method="imex_euler", dt0=0.05) as s:
+    with _solver(big, params, method="imex_euler", dt0=0.05, precision=precision) as s:
         s.set_state(cb, eb)
         s.autotune(1)
         fI, fE = s.rhs(s.get_state_hat())
@@ -370,14 +374,15 @@ def test_rhs_at_512_matches_oracle_on_a_band_limited_state(torch, params):
         idx = np.concatenate([np.arange(0, small // 2 + 1), np.arange(big - small // 2 + 1, big)])
         it = torch.from_numpy(idx).cuda()
         y_hat = s.get_state_hat()
-        for name, g, ref, out_tol in (("y", y_hat, Y, 1e-12), ("fI", fI, FI, None), ("fE", fE, FE, 1e-8)):
+        for name, g, ref, in_tol, out_tol in (("y", y_hat, Y, 1e-10, 1e-12), ("fI", fI, FI, 1e-10, None),
+                                              ("fE", fE, FE, fe_in, fe_out)):
             sub = g.index_select(1, it).index_select(2, it)[..., : small // 2 + 1]
             if ref is not None:
                 sub_np = sub.cpu().numpy() / float(big) ** 3
                 ref_n = ref / float(small) ** 3
                 for f in range(4):
                     rel = _rel(sub_np[f], ref_n[f])
-                    assert rel < 1e-10, (name, f, rel)
+                    assert rel < in_tol, (name, f, rel)
             if out_tol is None:
                 continue
             # nothing outside the band
