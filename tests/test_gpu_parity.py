@@ -424,9 +424,14 @@ def test_ark4_step_at_256_adaptive_workload_matches_oracle(torch, params):
 _LINEAR = {}
 
 
-def _linear_step(params, n, dt=0.1):
-    """Oracle side of the full-size linear-subproblem step (computed once per n)."""
-    if n not in _LINEAR:
+_TABLES = {"ark436l": oark.ark436l2sa, "ark2": oark.ark2, "ark324l": oark.ark324l2sa}
+
+
+def _linear_step(params, n, method="ark436l", dt=0.1):
+    """Oracle side of the full-size linear-subproblem step (computed once per
+    grid and method)."""
+    key = (n, method)
+    if key not in _LINEAR:
         _LINEAR.clear()     # one grid's arrays at a time
         rng = np.random.default_rng(31)
         c = 0.16 + 0.01 * rng.standard_normal((1, n, n, n))
@@ -434,18 +439,20 @@ def _linear_step(params, n, dt=0.1):
         del c
         m = om.Model((n, n, n), params)
         L = m.implicit_symbol()[0:1].copy()
-        y_new, lte, _ = oark.ark_step(yc, dt, oark.ark436l2sa(), lambda z: 0.0, L)
+        y_new, lte, _ = oark.ark_step(yc, dt, _TABLES[method](), lambda z: 0.0, L)
         del L
         # the error vector has 4 N^3 entries, three fields of them zero
         err_ref = oark.wrms_kspace(lte, yc, 1e-6, 1e-9, m.mult, m.N3) / 2.0
-        _LINEAR[n] = (dt, yc, y_new[0], err_ref)
-    return _LINEAR[n]
+        _LINEAR[key] = (dt, yc, y_new[0], err_ref)
+    return _LINEAR[key]
 
 
-@pytest.mark.parametrize("n,precision", [(512, "fp64"), (512, "mixed"), (504, "fp64")])
-def test_ark4_step_at_full_size_on_the_linear_subproblem(torch, params, n, precision):
-    """A whole ARK4(3)6L step at 512^3 (and at the paper's 504^3, radix-6/7
-    lines) in the bench's launch configuration
+@pytest.mark.parametrize("n,precision,method", [(512, "fp64", "ark436l"), (512, "mixed", "ark436l"),
+                                                (512, "fp64", "ark2"), (512, "fp64", "ark324l"),
+                                                (504, "fp64", "ark436l")])
+def test_step_at_full_size_on_the_linear_subproblem(torch, params, n, precision, method):
+    """A whole ARK4(3)6L step at 512^3 (also ARK2 and ARK3(2)4L, and at the
+    paper's 504^3, radix-6/7 lines) in the bench's launch configuration
     (tuned tile plans): every stage combination, the implicit solves, the
     first-stage F^I formed from the state, the update and error sums of the
     last stage and the update kernel, against the oracle's integrator.  With
@@ -455,9 +462,9 @@ def test_ark4_step_at_full_size_on_the_linear_subproblem(torch, params, n, preci
     y' = L(k) y mode by mode: the oracle's ark_step with a zero explicit part
     gives the state and the error.  The eta fields must stay exactly zero and
     the mass mode bitwise unchanged; the stage sums are FP64 in both forms."""
-    _say("ark4 step, linear subproblem", n, precision)
-    dt, yc, y_new, err_ref = _linear_step(params, n)
-    with _solver(n, params, method="ark436l", dt0=dt, precision=precision) as s:
+    _say("step, linear subproblem", n, precision, method)
+    dt, yc, y_new, err_ref = _linear_step(params, n, method)
+    with _solver(n, params, method=method, dt0=dt, precision=precision) as s:
         t = s.kspace_empty(4)
         t.zero_()
         t[0, :, :, : s.nxh] = torch.from_numpy(yc[0]).cuda()
