@@ -169,8 +169,10 @@ def cpu_baseline(n=128):
                        "%.1f s; host %s" % (n, wall, platform.processor() or platform.machine()))
 
 
-def ensemble_bench(torch, count, t_final, rtol, atol, ref_members, precisions=("fp64", "mixed")):
-    """64 uneven members: batched (one launch per pass, graph replay) vs one after another."""
+def ensemble_bench(torch, count, t_final, rtol, atol, ref_members, precisions=("fp64", "mixed"),
+                   batched_only=False):
+    """64 uneven members: batched (one launch per pass, graph replay) vs one after another
+    (batched_only: the batched runs alone, e.g. under a counter profiler)."""
     import pfinputs
     from paper_2609_36100_amd import Ensemble, Solver
     mem = pfinputs.ensemble_members(count)
@@ -196,6 +198,9 @@ def ensemble_bench(torch, count, t_final, rtol, atol, ref_members, precisions=("
         out["batched_" + prec] = dict(wall_s=round(wall, 3), value=round(stages / wall / 1e6, 1),
                                       steps=sum(s["steps"] for s in st), rejects=sum(s["rejects"] for s in st),
                                       block_threads={k: v["block_threads"] for k, v in tun.items()})
+        out["batched_" + prec]["member_point_stages"] = stages
+    if batched_only:
+        return out
     log("ensemble sequential plain fp64")
     wall = 0.0
     stages = 0
@@ -557,6 +562,8 @@ def main():
     ap.add_argument("--rtol", type=float, default=1e-6, help="time_to_t: relative tolerance (atol = rtol / 1000)")
     ap.add_argument("--t-final", type=float, default=None)
     ap.add_argument("--members", type=int, default=64)
+    ap.add_argument("--batched-only", action="store_true",
+                    help="ensemble: the batched runs alone (no sequential or reference runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 4 GiB (counter calibration)")
     args = ap.parse_args()
@@ -581,7 +588,8 @@ def main():
                           "copy_bytes_written_per_launch": src.numel() * 8, "launches": 3}))
         return
     if args.mode == "ensemble":
-        r = ensemble_bench(torch, args.members, args.t_final or 100.0, 1e-6, 1e-9, ref_members=8)
+        r = ensemble_bench(torch, args.members, args.t_final or 100.0, 1e-6, 1e-9, ref_members=8,
+                           batched_only=args.batched_only)
         print(json.dumps({"metric": METRIC, "mode": "ensemble", "unit": "Mpts·stages/s",
                           "value": r["batched_fp64"]["value"], "n_gpus": 1, "dtype": "f64",
                           "data": "synthetic", "higher_is_better": True,
