@@ -16,21 +16,30 @@ order study cites; their coefficients are the published rationals.
 
 Readings (where the paper leaves a choice): the WRMS vector is the reciprocal-space state
 scaled to unit norm (Parseval), modes weighted by their half-spectrum
-multiplicity; the step-size controller, which the paper leaves to the
-library, is the elementary I-controller ``dt * min(5, max(0.2, 0.9 err^(-1/(q+1))))``
-with embedding order q, growth capped at 1 after a rejection and a factor 0.25
-after a non-finite result.
+multiplicity (default), or the real-space state itself (``norm_space = 1``:
+the norm and weights of Eqs. wrms_norm / wrms_weights applied point by point
+to the four real fields); the step-size controller, which the paper leaves to
+the library, is the elementary I-controller
+``dt * min(5, max(0.2, 0.9 err^(-1/(q+1))))`` with embedding order q, a factor
+0.25 after a non-finite result, and no growth (factor at most 1) for the step
+proposed after an accepted attempt that directly follows a rejected one
+(Hairer, Norsett & Wanner, Solving ODEs I, section II.4: facmax = 1 right after
+a rejection).
 
 Pinned by tests/test_oracle_ark.py: order conditions in exact rational
 arithmetic, row sums, the closed-form stability function on a scalar linear
-test problem, IMEX Euler against its direct formula, WRMS on hand vectors,
-observed convergence orders.
+test problem, IMEX Euler against its direct formula, WRMS on hand vectors
+(both norm spaces, the k-space norm with a relative tolerance on a hand-worked
+single-mode case), observed convergence orders, and the controller's
+reject-accept sequence in the time loop.
 """
 from __future__ import annotations
 
 from fractions import Fraction as Fr
 
 import numpy as np
+
+from . import spectral as sp
 
 
 class Table:
@@ -283,8 +292,21 @@ def wrms_kspace(lte_hat, y_prev_hat, rtol, atol, mult, n3):
     return float(np.sqrt(tot / (nf * n3)))
 
 
+def wrms_real(lte_hat, y_prev_hat, rtol, atol, shape):
+    """WRMS of the error in real space (``norm_space = 1``): Eq. wrms_norm with the
+    weights of Eq. wrms_weights taken point by point over every real field, vector
+    length ``fields * N^3``."""
+    e = sp.irfft3(lte_hat, shape)
+    yp = sp.irfft3(y_prev_hat, shape)
+    return wrms(e, wrms_weights(yp, rtol, atol))
+
+
 def controller(dt, err, q, after_reject=False):
-    """Elementary I-controller: next step size from the WRMS error estimate."""
+    """Elementary I-controller: next step size from the WRMS error estimate.
+
+    ``after_reject``: this attempt was accepted and the one before it was
+    rejected; the proposal then does not grow (factor capped at 1).
+    """
     if not np.isfinite(err):
         return 0.25 * dt
     if err == 0.0:
@@ -300,7 +322,7 @@ class Integrator:
     """Fixed or adaptive time loop over :func:`ark_step` (host-side control, FP64)."""
 
     def __init__(self, model, table="ark436l", adaptive=False, dt0=1e-2, rtol=1e-6,
-                 atol=1e-9, dt_min=0.0, dt_max=np.inf, max_rejects=10):
+                 atol=1e-9, dt_min=0.0, dt_max=np.inf, max_rejects=10, norm_space=0):
         self.model = model
         self.table = TABLES[table]() if isinstance(table, str) else table
         self.adaptive = bool(adaptive)
@@ -310,8 +332,11 @@ class Integrator:
         self.rtol, self.atol = float(rtol), float(atol)
         self.dt_min, self.dt_max = float(dt_min), float(dt_max)
         self.max_rejects = int(max_rejects)
+        self.norm_space = int(norm_space)
         self.Lsym = model.implicit_symbol()
-        self.stats = dict(steps=0, attempts=0, rejects=0, n_rhs=0, dts=[], errs=[])
+        self.prev_rejected = False
+        # log: one (t, dt, err, accepted, dt_next) tuple per attempt
+        self.stats = dict(steps=0, attempts=0, rejects=0, n_rhs=0, dts=[], errs=[], log=[])
 
     def attempt(self, y, dt):
         y_new, lte, n_exp = ark_step(y, dt, self.table, self.model.f_explicit, self.Lsym)
@@ -319,14 +344,16 @@ class Integrator:
         self.stats["attempts"] += 1
         err = 0.0
         if lte is not None:
-            err = wrms_kspace(lte, y, self.rtol, self.atol, self.model.mult, self.model.N3)
+            if self.norm_space == 1:
+                err = wrms_real(lte, y, self.rtol, self.atol, self.model.shape)
+            else:
+                err = wrms_kspace(lte, y, self.rtol, self.atol, self.model.mult, self.model.N3)
         finite = bool(np.all(np.isfinite(y_new))) and np.isfinite(err)
         return y_new, (err if finite else np.inf)
 
     def advance(self, y, t, t_final, dt_sequence=None):
         """Integrate from t to t_final; returns (y, t).  Replays ``dt_sequence`` if given."""
         rejects = 0
-        after_reject = False
         seq = list(dt_sequence) if dt_sequence is not None else None
         while t < t_final * (1.0 - 1e-15) and (seq is None or seq):
             dt = seq.pop(0) if seq is not None else min(self.dt, self.dt_max)
@@ -334,10 +361,13 @@ class Integrator:
             y_new, err = self.attempt(y, dt)
             ok = np.isfinite(err) and (not self.adaptive or err <= 1.0 or seq is not None)
             if self.adaptive:
-                self.dt = controller(dt, err, self.table.emb_order, after_reject=not ok)
+                cap = ok and self.prev_rejected
+                self.dt = controller(dt, err, self.table.emb_order, after_reject=cap)
                 self.dt = max(self.dt, self.dt_min)
+                self.prev_rejected = not ok
             elif not np.isfinite(err):
                 raise FloatingPointError("non-finite state in fixed-step run")
+            self.stats["log"].append((t, dt, err, bool(ok), self.dt))
             if ok:
                 y, t = y_new, t + dt
                 self.stats["steps"] += 1

@@ -10,8 +10,11 @@
   variant (fraction of points with ``max_v eta_v > 0.5``).
 
 Pinned by tests/test_oracle_model.py (energy against an explicit displacement
-solve in real space; RHS against finite differences of this energy) and
-tests/test_oracle_ark.py (monotone decrease under IMEX Euler).
+solve in real space; RHS against finite differences of this energy),
+tests/test_oracle_ark.py (monotone decrease under IMEX Euler) and
+tests/test_oracle_diagnostics.py (volume fraction: uniform fields against h
+worked by hand, disjoint boxes counted by hand, a smooth field's closed-form
+mean; the threshold variant's counts; mass as the mean of c).
 """
 from __future__ import annotations
 

@@ -189,6 +189,56 @@ def test_kspace_wrms_equals_realspace_rms_for_uniform_weights():
     assert got == pytest.approx(ref, rel=1e-13)
 
 
+def test_wrms_kspace_relative_tolerance_single_mode():
+    """k-space WRMS with rtol > 0, worked by hand on one Fourier mode.
+
+    Error and previous state live in eta_1 only: e(r) = a cos(2 pi x / 8) and
+    y(r) = b cos(2 pi x / 8) on an 8^3 grid.  A cosine of amplitude A puts
+    A N^3 / 2 into the half-spectrum bin kx = 1 (and nothing elsewhere), so
+    the unitary coefficients are E = a sqrt(N^3) / 2 and Y = b sqrt(N^3) / 2;
+    the bin stands for two full-spectrum modes (kx = +-1).  With the reading's
+    weight w = 1 / (rtol |Y| + atol) and vector length 4 N^3:
+    WRMS^2 = 2 (E w)^2 / (4 N^3)."""
+    n3 = 512.0
+    a, b, rtol, atol = 1e-3, 0.5, 1e-2, 1e-4
+    x = np.arange(8.0)
+    shape = (8, 8, 8)
+    e = np.zeros((4,) + shape)
+    y = np.zeros((4,) + shape)
+    e[1] = a * np.cos(2 * np.pi * x / 8)[None, None, :]
+    y[1] = b * np.cos(2 * np.pi * x / 8)[None, None, :]
+    E_hat, Y_hat = sp.rfft3(e), sp.rfft3(y)
+    # hand values: sqrt(512) / 2 = 8 sqrt(2)
+    E = a * 8 * np.sqrt(2.0)
+    Y = b * 8 * np.sqrt(2.0)
+    w = 1.0 / (rtol * Y + atol)
+    expect = np.sqrt(2 * (E * w) ** 2 / (4 * n3))
+    got = ark.wrms_kspace(E_hat, Y_hat, rtol, atol, sp.multiplicity(shape), n3)
+    assert got == pytest.approx(expect, rel=1e-13)
+    # a slip of one factor sqrt(N^3) in the weight's state term changes it by orders of magnitude
+    assert abs(got - np.sqrt(2 * (E / (rtol * Y * np.sqrt(n3) + atol)) ** 2 / (4 * n3))) > 0.5 * got
+
+
+def test_wrms_real_space_hand_values_and_parseval():
+    """norm_space = 1: constant error alpha in c only, constant state beta in
+    every field: WRMS = sqrt(((alpha / (rtol beta + atol))^2 N^3) / (4 N^3));
+    with rtol = 0 it equals the k-space norm (Parseval)."""
+    shape = (6, 8, 10)
+    alpha, beta, rtol, atol = 2e-4, 0.3, 1e-3, 1e-5
+    e = np.zeros((4,) + shape)
+    e[0] = alpha
+    y = np.full((4,) + shape, beta)
+    got = ark.wrms_real(sp.rfft3(e), sp.rfft3(y), rtol, atol, shape)
+    assert got == pytest.approx(0.5 * alpha / (rtol * beta + atol), rel=1e-12)
+    rng = np.random.default_rng(3)
+    e = rng.standard_normal((4,) + shape)
+    y = rng.standard_normal((4,) + shape)
+    E, Y = sp.rfft3(e), sp.rfft3(y)
+    k = ark.wrms_kspace(E, Y, 0.0, 1e-3, sp.multiplicity(shape), np.prod(shape))
+    r = ark.wrms_real(E, Y, 0.0, 1e-3, shape)
+    assert r == pytest.approx(k, rel=1e-13)
+
+
 def test_controller_rules():
     assert ark.controller(1.0, 0.0, 3) == 5.0
     assert ark.controller(1.0, 1e9, 3) == pytest.approx(0.2)
@@ -301,6 +351,38 @@ def test_observed_order_nonlinear_self_convergence(params):
             errs.append(np.sqrt(np.mean((sp.irfft3(yy, m.shape) - uref) ** 2)))
         s = _order_slope(errs, dts)
         assert lo <= s <= hi, (table, s, errs)
+
+
+def test_no_growth_after_a_rejection_in_the_loop(params):
+    """Time-loop level: an accepted attempt that follows a rejected one
+    proposes no larger step (Hairer-Norsett-Wanner facmax = 1); an accepted
+    attempt after an accepted one may grow; a rejected attempt shrinks by the
+    controller factor max(0.2, 0.9 err^(-1/4))."""
+    n = 16
+    spec, c, eta = pfinputs.config("small32", n=n)
+    m = om.Model((n, n, n), params)
+    y = om.to_kspace(c, eta)
+    integ = ark.Integrator(m, table="ark436l", adaptive=True, dt0=5.0, rtol=1e-6, atol=1e-9)
+    integ.advance(y, 0.0, 6.0)
+    log = integ.stats["log"]
+    after_reject = [i for i in range(1, len(log)) if log[i][3] and not log[i - 1][3]]
+    after_accept = [i for i in range(1, len(log)) if log[i][3] and log[i - 1][3]]
+    assert after_reject and after_accept
+    for i in after_reject:
+        t, dt, err, ok, nxt = log[i]
+        assert nxt <= dt, (i, dt, nxt)
+        # the cap is what binds here: the plain factor would have grown the step
+        if err < (0.9) ** 4:
+            assert nxt == dt
+    assert any(log[i][4] > log[i][1] for i in after_accept)
+    for t, dt, err, ok, nxt in log:
+        if not ok:
+            assert nxt == pytest.approx(dt * max(0.2, 0.9 * err ** -0.25), rel=1e-15)
+    # every step right after a reject/accept pair: dt_k = the proposal made at k-1
+    for i in range(1, len(log)):
+        prev_next = log[i - 1][4]
+        t, dt, err, ok, nxt = log[i]
+        assert dt == pytest.approx(min(prev_next, 6.0 - t), rel=1e-15)
 
 
 def test_adaptive_loop_reaches_final_time_and_rejects(params):
