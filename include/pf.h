@@ -89,6 +89,14 @@ typedef struct {
   int32_t adaptive;         /* 1: embedded-error step control (ARK2, ARK324L, ARK436L) */
   double dt0, rtol, atol, dt_min, dt_max;
   int32_t max_rejects;      /* consecutive rejections before PF_ERR_STEP_FAIL */
+  /* Vector the WRMS norm of Eqs. wrms_norm / wrms_weights is taken over:
+   * 0 (default): the 4 fields' reciprocal-space coefficients scaled to a
+   *   unitary transform, each half-spectrum mode counted with its
+   *   multiplicity, weights (rtol |Y_{n-1}| + atol)^-1 per coefficient;
+   * 1: the 4 real fields point by point, weights (rtol |y_{n-1}(r)| + atol)^-1
+   *   (the paper applies the test to the change of the fields; two extra
+   *   inverse 3D transforms of 4 fields per attempted step, single grids only). */
+  int32_t norm_space;
 } pf_params;
 
 typedef struct {
@@ -103,45 +111,64 @@ typedef struct {
   double err_last;     /* WRMS error estimate of the last attempt */
   double mass;         /* mean of c (k = 0 coefficient / N^3) */
   double elapsed_ms;   /* device time spent in pf_advance / pf_ark_step */
+  double F;            /* total free energy (Eq. 1 on the grid; see pf_free_energy) */
+  double vf;           /* precipitate volume fraction: mean of H = sum_v h(eta_v) */
+  double vf_threshold; /* fraction of points with max_v eta_v > 1/2 */
 } pf_stats;
 
-/* Fills p with the defaults of the stand-in model: W=w=kappa=M=L=1,
- * c_m=0.02, c_p=0.25, C=(250,150,120), eigenstrain 0.0286 along the variant
- * axis and 0.0067 on the others, dx=1, ARK4(3)6L, FP64, fixed step 1e-2.
- * Never fails for non-NULL p. */
+/* Fills p with the defaults of the stand-in model (Methods, "Phase-field
+ * model formulation", restricted to one stiffness and a per-variant double
+ * well): W=w=kappa=M=L=1, c_m=0.02, c_p=0.25, C=(250,150,120), eigenstrain
+ * 0.0286 along the variant axis and 0.0067 on the others, dx=1, ARK4(3)6L
+ * (the fourth-order pair of Methods, "Time integration"), FP64, fixed step
+ * 1e-2, k-space WRMS.  PF_ERR_ARG for NULL p, else PF_OK. */
 pf_status pf_default_params(pf_params* p);
 
 /* Returns 1 if n is a supported grid length (the list under pf_params),
- * else 0. */
+ * else 0: the line lengths the 3D real FFT of the pseudospectral
+ * discretisation (Methods, "MEUMAPPS C++ and the MEUMAPPS-SS application")
+ * is compiled for.  Never fails. */
 int32_t pf_size_supported(int32_t n);
 
 /* Creates a context for the grid and model in *p on the current device and
- * allocates its workspace (state, stage arrays, FFT temporaries).
- * hip_stream: a hipStream_t or NULL.  On success *out owns the workspace.
- * Errors: PF_ERR_ARG (bad parameter), PF_ERR_UNSUPPORTED_SIZE, PF_ERR_OOM. */
+ * allocates its workspace: the state vector and the stage derivative arrays
+ * of the ImEx-ARK pair (Eq. ARK_method), FFT temporaries, reductions.  The
+ * state is the reciprocal-space vector the integrator advances (Methods,
+ * "Time integration": the state is held in the fields' reciprocal-space
+ * coefficients, device-resident throughout).  hip_stream: a hipStream_t or
+ * NULL (default stream).  On success *out owns the workspace; release it
+ * with pf_finalize.  Errors: PF_ERR_ARG (NULL pointer or bad parameter),
+ * PF_ERR_UNSUPPORTED_SIZE, PF_ERR_OOM, PF_ERR_HIP (no usable device). */
 pf_status pf_init(const pf_params* p, void* hip_stream, pf_ctx** out);
 
 /* Frees the context and its workspace (NULL is a no-op). */
 void pf_finalize(pf_ctx* ctx);
 
-/* Row pitch kp (complex elements) of every reciprocal-space array. */
+/* Row pitch kp (complex elements) of every reciprocal-space array (the
+ * half spectrum of the real transform, padded; 0 for NULL). */
 int64_t pf_kspace_pitch(const pf_ctx* ctx);
 
-/* Bytes of device workspace the context holds. */
+/* Bytes of device workspace the context holds (0 for NULL). */
 int64_t pf_workspace_bytes(const pf_ctx* ctx);
 
-/* Sets the state from real-space fields (transformed to reciprocal space).
- * c: N = nz*ny*nx values; eta: 3N values; host or device per on_device.
- * Resets t to t0. */
+/* Sets the state vector from real-space fields: composition c and order
+ * parameters eta_1..3 (Methods, "Time integration": the state is built from
+ * the composition and order-parameter fields), transformed to reciprocal
+ * space.  c: N = nz*ny*nx values; eta: 3N values; host or device per
+ * on_device (both caller-owned, read only).  Resets t to t0 and the step
+ * controller's memory of a rejection.  Errors: PF_ERR_ARG, PF_ERR_HIP. */
 pf_status pf_set_state(pf_ctx* ctx, const double* c, const double* eta,
                        int32_t on_device, double t0);
 
 /* Writes the real-space state into c (N values) and eta (3N values), host or
- * device per on_device (inverse transform of the reciprocal-space state). */
+ * device per on_device (inverse transform of the reciprocal-space state,
+ * Methods, "MEUMAPPS C++ and the MEUMAPPS-SS application").  Errors:
+ * PF_ERR_ARG, PF_ERR_HIP. */
 pf_status pf_get_state(pf_ctx* ctx, double* c, double* eta, int32_t on_device);
 
-/* Copies the reciprocal-space state to / from device memory y_hat
- * (layout above). */
+/* Copies the reciprocal-space state vector (Methods, "Time integration") to
+ * / from caller-owned device memory y_hat (layout above); set resets t to
+ * t0.  Errors: PF_ERR_ARG, PF_ERR_HIP. */
 pf_status pf_get_state_hat(pf_ctx* ctx, void* y_hat_device);
 pf_status pf_set_state_hat(pf_ctx* ctx, const void* y_hat_device, double t0);
 
@@ -169,24 +196,51 @@ pf_status pf_ark_step(pf_ctx* ctx, double dt, double* dt_next, double* err_wrms,
  * PF_ERR_STEP_FAIL after max_rejects consecutive rejections. */
 pf_status pf_advance(pf_ctx* ctx, double t_final, pf_stats* out);
 
+/* Counters of the integrator (accepted / attempted / rejected steps and
+ * explicit RHS evaluations, the cost measure of Results, "Improved
+ * performance via time integration approach"), step sizes, and the state's
+ * diagnostics: mass, total free energy F and volume fraction (as
+ * pf_free_energy and pf_diagnostics; about the cost of one RHS evaluation).
+ * pf_advance fills its *out the same way.  Errors: PF_ERR_ARG, PF_ERR_HIP. */
 pf_status pf_get_stats(pf_ctx* ctx, pf_stats* out);
 
-/* Current time and the proposed next step size. */
+/* Current time (0 for NULL); pf_set_dt sets the next attempted step size
+ * (PF_ERR_ARG unless dt > 0). */
 double pf_get_time(const pf_ctx* ctx);
 pf_status pf_set_dt(pf_ctx* ctx, double dt);
 
-/* Mean of c, mean of H = sum_v h(eta_v) (precipitate volume fraction) and the
- * fraction of points with max_v eta_v > 0.5, from the current state. */
+/* Mean of c, mean of H = sum_v h(eta_v) (precipitate volume fraction, with
+ * the interpolation function h of Methods, "Phase-field model formulation")
+ * and the fraction of points with max_v eta_v > 0.5, from the current state,
+ * in FP64.  Output pointers may be NULL.  Errors: PF_ERR_ARG, PF_ERR_STATE
+ * (no state set), PF_ERR_HIP. */
 pf_status pf_diagnostics(pf_ctx* ctx, double* mass, double* vf, double* vf_threshold);
 
-/* Standalone 3D real FFT of nf fields (the transform every stage uses).
+/* Total free energy of the current state (Eq. 1 with the stand-in model's
+ * bulk density f, isotropic gradient energies and the elastic energy at
+ * mechanical equilibrium, Eq. u_gov), in FP64 on the grid:
+ *   F = dx^3 [ sum_r f(c, eta) + 1/(2 N^3) sum_k m(k) k^2 (kappa_c |c~|^2
+ *       + kappa_eta sum_v |eta~_v|^2) + 1/(2 N^3) sum_k m(k) sum_vw
+ *       B_vw(k) Re(th~_v conj th~_w) + mean-strain terms ],
+ * th_v = h(eta_v), m(k) the half-spectrum multiplicity, B the per-wavevector
+ * elastic kernel (its k = 0 value per mean_strain_mode); with a prescribed
+ * mean strain the terms N^3/2 eps_bar:C:eps_bar - eps_bar:C:sum_v
+ * eps*_v th~_v(0).  F is the Lyapunov functional of the gradient flow
+ * (Eqs. x_gov, phi_gov).  Errors: PF_ERR_ARG, PF_ERR_STATE, PF_ERR_HIP. */
+pf_status pf_free_energy(pf_ctx* ctx, double* F);
+
+/* Standalone 3D real FFT of nf fields (the transform every stage uses to
+ * move fields between real and reciprocal space, Methods, "MEUMAPPS C++ and
+ * the MEUMAPPS-SS application"; errors PF_ERR_ARG, PF_ERR_HIP).
  * dir = -1: real [nf][nz][ny][nx] -> reciprocal [nf][nz][ny][kp] (unnormalised);
  * dir = +1: reciprocal -> real, scaled by 1/(nx ny nz).
  * in/out: device; nf in 1..4; in and out must not overlap.  The inverse
  * overwrites `in` (it is used as the intermediate). */
 pf_status pf_fft3d(pf_ctx* ctx, int32_t dir, int32_t nf, void* in, void* out);
 
-/* Per-kernel-class timing with HIP events on the context's stream.
+/* Per-kernel-class timing with HIP events on the context's stream (the
+ * profile breakdown of Results, "Improved performance via GPU acceleration",
+ * by kernel class).
  * pf_profile_enable(ctx, on) clears the counters and turns recording on/off.
  * Classes 0 .. pf_profile_classes()-1 are named by pf_profile_name (never
  * NULL; "" for an invalid class).  pf_profile_get returns the summed device
@@ -199,7 +253,9 @@ int32_t pf_profile_classes(void);
 const char* pf_profile_name(int32_t cls);
 pf_status pf_profile_get(pf_ctx* ctx, int32_t cls, double* total_ms, int64_t* launches, double* bytes);
 
-/* Autotuner for the FFT tile plans.  Every column (y/z) pass kind
+/* Autotuner for the FFT tile plans (the paper notes that the parallel-loop
+ * tiling was left untuned per architecture, Results, "Improved performance
+ * via GPU acceleration").  Every column (y/z) pass kind
  * ("colfft", "stage_invz", "zpass_elastic", "zpass_fwd_ac") has two tile
  * variants (kx columns per work-group; see pf_tuning_get); "colfft" has a
  * third for lines of 128 or more: the variant-1 tile in a persistent
@@ -220,9 +276,11 @@ pf_status pf_tuning_set(pf_ctx* ctx, int32_t kind, int32_t variant);
 pf_status pf_tuning_ms(pf_ctx* ctx, int32_t kind, int32_t variant, double* ms);
 
 /* ---- Batched ensembles (many independent simulations of uneven sizes) ----
+ * Ensembles of simulations are the use the paper points faster runs at
+ * (Discussion: uncertainty quantification over many runs).
  * n members, each with its own pf_params (cubic grids of 32, 48, 64, 96 or
  * 128 points; one embedded method (PF_ARK2, PF_ARK324L or PF_ARK436L), one
- * precision and one adaptivity setting for all).  Every pass of the stage cycle is one launch covering all members;
+ * precision and one adaptivity setting for all; norm_space 0).  Every pass of the stage cycle is one launch covering all members;
  * accept / reject and the next step size are decided on the device per
  * member; one attempted step of all members is captured once as a hipGraph
  * and replayed.  stream: a hipStream_t or NULL (then the ensemble creates its
@@ -234,15 +292,21 @@ int32_t pf_ensemble_size_supported(int32_t n);
 int64_t pf_ensemble_workspace_bytes(const pf_ens* ens);
 int64_t pf_ensemble_kspace_pitch(const pf_ens* ens, int32_t member);
 /* Per-member state access, as pf_set_state / pf_get_state / pf_get_state_hat /
- * pf_diagnostics on member m (0-based); set_state resets the member's time,
- * step size (dt0) and counters. */
+ * pf_diagnostics / pf_free_energy on member m (0-based; PF_ERR_ARG out of
+ * range); set_state resets the member's time, step size (dt0), controller
+ * memory and counters. */
 pf_status pf_ensemble_set_state(pf_ens* ens, int32_t m, const double* c, const double* eta,
                                 int32_t on_device, double t0);
 pf_status pf_ensemble_get_state(pf_ens* ens, int32_t m, double* c, double* eta, int32_t on_device);
 pf_status pf_ensemble_get_state_hat(pf_ens* ens, int32_t m, void* y_hat_device);
 pf_status pf_ensemble_diagnostics(pf_ens* ens, int32_t m, double* mass, double* vf, double* vf_threshold);
+pf_status pf_ensemble_free_energy(pf_ens* ens, int32_t m, double* F);
 /* Advances every member to its t_final[m] (host array of n values), at most
- * max_steps attempted steps (graph replays).  Fills per_member[n] if non-NULL.
+ * max_steps attempted steps (graph replays), with the step control of
+ * pf_advance per member (Eqs. ARK_embedding, wrms_norm, wrms_weights; a
+ * later call with larger t_final resumes from each member's proposed step).
+ * Fills per_member[n] if non-NULL (counters, step sizes, and each member's
+ * mass, F and volume fraction as pf_get_stats).
  * PF_ERR_STEP_FAIL if a member hit max_rejects consecutive rejections,
  * PF_ERR_NONFINITE for a non-finite fixed-step member, PF_ERR_STATE if
  * max_steps ran out first. */
@@ -259,6 +323,9 @@ pf_status pf_ensemble_tuning_get(pf_ens* ens, int32_t kind, int32_t* block_threa
 pf_status pf_ensemble_tuning_set(pf_ens* ens, int32_t kind, int32_t block_threads);
 
 /* ---- Fourier neural operator surrogate (learned form) --------------------
+ * A learned form beside the method (the paper has no learned component; it
+ * advances ensemble members where the plain integrator of Methods, "Time
+ * integration" would, and that integrator judges it).
  * Maps the real-space state (cin = 4 fields c, eta_1..3 on an n^3 grid,
  * planar [field][z][y][x]) to the state a fixed time later: the network
  * predicts the increment divided by a per-channel scale.  Layers:
@@ -276,12 +343,27 @@ typedef struct {
   int32_t n, width, modes, layers, hidden, cin, cout;
 } pf_fno_config;
 typedef struct pf_fno pf_fno;
+/* Creates a network with zero parameters and its device workspace
+ * (activations, spectral blocks, gradients, Adam moments) on the current
+ * device; hip_stream a hipStream_t or NULL.  Release with pf_fno_destroy
+ * (NULL is a no-op).  Errors: PF_ERR_ARG (config outside the constraints),
+ * PF_ERR_OOM, PF_ERR_HIP. */
 pf_status pf_fno_create(const pf_fno_config* cfg, void* hip_stream, pf_fno** out);
 void pf_fno_destroy(pf_fno* f);
+/* Number of parameters (0 for NULL). */
 int64_t pf_fno_num_params(const pf_fno* f);
-/* host float32 arrays of pf_fno_num_params values; set also resets Adam */
+/* Host float32 arrays of pf_fno_num_params values (caller-owned); set also
+ * resets Adam.  Errors for the calls below: PF_ERR_ARG for NULL pointers,
+ * PF_ERR_HIP for a failed HIP call.  Device arrays are caller-owned and
+ * ordered on the network's stream. */
 pf_status pf_fno_set_params(pf_fno* f, const float* host_params);
 pf_status pf_fno_get_params(pf_fno* f, float* host_params);
+/* Loads trained weights from a host buffer of `bytes` bytes holding the flat
+ * parameter vector (order as above) either as float32 (bytes = 4 x
+ * pf_fno_num_params) or as bfloat16 (bytes = 2 x pf_fno_num_params; widened
+ * to the float32 master copy exactly).  Resets Adam.  PF_ERR_ARG for any
+ * other size or a NULL pointer. */
+pf_status pf_fno_load(pf_fno* f, const void* host_weights, size_t bytes);
 /* per-channel output scale (cout host floats); the target is (y - x) / scale */
 pf_status pf_fno_set_scale(pf_fno* f, const float* host_scale);
 /* per-channel input normalisation (cin host floats each): the network sees
@@ -298,6 +380,14 @@ pf_status pf_fno_get_grad(pf_fno* f, float* host_grad);
 pf_status pf_fno_zero_grad(pf_fno* f);
 /* Adam step with the accumulated gradient times grad_scale; zeroes it */
 pf_status pf_fno_adam_step(pf_fno* f, float lr, float beta1, float beta2, float eps, float grad_scale);
+/* One training step on a batch: zero the gradient, forward + loss + backward
+ * for each of the `batch` pairs (x, y each device float32
+ * [batch][cin][n^3], the state and the state a fixed time later), then one
+ * Adam step (beta1 0.9, beta2 0.999, eps 1e-8) with the gradient averaged
+ * over the batch and learning rate lr.  *loss (may be NULL) receives the
+ * batch's mean loss before the update.  PF_ERR_ARG for batch < 1, NULL x/y
+ * or lr not positive and finite. */
+pf_status pf_fno_train_step(pf_fno* f, const float* x, const float* y, int32_t batch, float lr, float* loss);
 /* surrogate advance: next = state + scale * net(state), then the mean of c is
  * restored (the composition is conserved); state / next device float64
  * [cin][n^3] (cin == cout); next may equal state */
@@ -331,7 +421,10 @@ typedef struct {
 pf_status pf_fno_advance(pf_fno* f, pf_ctx* plain, double* state, int32_t n_adv, double delta,
                          int32_t check_every, double tol, pf_fno_stats* stats);
 /* ||a - b||_2 / ||b||_2 over n device float64 values (||a - b|| if b == 0),
- * ordered on hip_stream (NULL = default); synchronises that stream. */
+ * the error measure of the surrogate's checks; ordered on hip_stream (NULL =
+ * default); synchronises that stream.  Allocates its partial sums (device
+ * and pinned host) per call.  Errors: PF_ERR_ARG (NULL pointer, n < 1),
+ * PF_ERR_OOM, PF_ERR_HIP. */
 pf_status pf_rel_l2(const double* a, const double* b, int64_t n, void* hip_stream, double* out);
 
 /* Streaming-bandwidth probe (a measurement aid, not part of the method): on
@@ -345,6 +438,11 @@ pf_status pf_bandwidth_probe(int64_t bytes, int32_t reps, void* hip_stream, doub
 
 /* Human-readable status name; never NULL. */
 const char* pf_status_string(pf_status s);
+
+/* Identifier of the sources the library was built from (a hash over the
+ * kernel, runtime and header sources, fixed at build time); never NULL.
+ * Bindings compare it with the sources beside them to refuse a stale build. */
+const char* pf_build_id(void);
 
 #ifdef __cplusplus
 }

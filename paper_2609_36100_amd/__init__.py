@@ -172,6 +172,12 @@ class Solver:
                    "pf_diagnostics")
         return dict(mass=m.value, vf=v.value, vf_threshold=vt.value)
 
+    def free_energy(self):
+        """Total free energy F of the current state (computed by libpf in FP64)."""
+        F = ctypes.c_double()
+        _lib.check(_lib.lib().pf_free_energy(self._h, ctypes.byref(F)), "pf_free_energy")
+        return F.value
+
     # -- tile plans -------------------------------------------------------------
     def autotune(self, reps=3):
         """Time the tile variants of every column pass and keep the fastest."""
@@ -297,6 +303,11 @@ class Ensemble:
                                                       ctypes.byref(c)), "pf_ensemble_diagnostics")
         return dict(mass=a.value, vf=b.value, vf_threshold=c.value)
 
+    def free_energy(self, m):
+        F = ctypes.c_double()
+        _lib.check(_lib.lib().pf_ensemble_free_energy(self._h, int(m), ctypes.byref(F)), "pf_ensemble_free_energy")
+        return F.value
+
     def advance(self, t_final, max_steps=100000):
         """Advance every member to t_final (scalar or per member); returns per-member stats."""
         tf = np.broadcast_to(np.asarray(t_final, dtype=np.float64), (self.M,)).copy()
@@ -382,6 +393,19 @@ class FNO:
         th = np.ascontiguousarray(theta, dtype=np.float32)
         assert th.size == self.num_params
         _lib.check(_lib.lib().pf_fno_set_params(self._h, th.ctypes.data_as(ctypes.c_void_p)), "pf_fno_set_params")
+
+    def load(self, weights):
+        """Load a flat parameter vector given as float32 or bfloat16 bytes / numpy array
+        (bfloat16 as uint16 bit patterns)."""
+        buf = weights.tobytes() if isinstance(weights, np.ndarray) else bytes(weights)
+        _lib.check(_lib.lib().pf_fno_load(self._h, ctypes.c_char_p(buf), len(buf)), "pf_fno_load")
+
+    def train_step(self, x, y, lr):
+        """One Adam step on a batch (x, y: device float32 (batch, cin, n, n, n)); returns the mean loss."""
+        loss = ctypes.c_float()
+        _lib.check(_lib.lib().pf_fno_train_step(self._h, _ptr(x.contiguous()), _ptr(y.contiguous()), int(x.shape[0]),
+                                                float(lr), ctypes.byref(loss)), "pf_fno_train_step")
+        return loss.value
 
     def get_params(self):
         th = np.empty(self.num_params, np.float32)

@@ -10,6 +10,8 @@ from __future__ import annotations
 import ctypes
 import os
 
+from .build import source_id
+
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libpf.so")
 
@@ -38,6 +40,7 @@ class Params(ctypes.Structure):
         ("dt0", ctypes.c_double), ("rtol", ctypes.c_double), ("atol", ctypes.c_double),
         ("dt_min", ctypes.c_double), ("dt_max", ctypes.c_double),
         ("max_rejects", ctypes.c_int32),
+        ("norm_space", ctypes.c_int32),
     ]
 
 
@@ -65,6 +68,7 @@ class Stats(ctypes.Structure):
         ("dt_min_seen", ctypes.c_double), ("dt_max_seen", ctypes.c_double),
         ("err_last", ctypes.c_double), ("mass", ctypes.c_double),
         ("elapsed_ms", ctypes.c_double),
+        ("F", ctypes.c_double), ("vf", ctypes.c_double), ("vf_threshold", ctypes.c_double),
     ]
 
     def as_dict(self):
@@ -100,6 +104,12 @@ _SIGS = {
                                       ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
     "pf_fft3d": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]),
     "pf_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "pf_build_id": (ctypes.c_char_p, []),
+    "pf_free_energy": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]),
+    "pf_ensemble_free_energy": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]),
+    "pf_fno_load": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t]),
+    "pf_fno_train_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                                         ctypes.c_float, ctypes.POINTER(ctypes.c_float)]),
     "pf_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "pf_tuning_kinds": (ctypes.c_int32, []),
     "pf_tuning_name": (ctypes.c_char_p, [ctypes.c_int32]),
@@ -161,7 +171,8 @@ _SIGS = {
 
 
 def lib():
-    """Load libpf.so (raises ImportError with instructions when it is missing)."""
+    """Load libpf.so (raises ImportError with instructions when it is missing or
+    was built from sources other than those beside it)."""
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
@@ -172,6 +183,11 @@ def lib():
             fn = getattr(L, name)
             fn.restype = res
             fn.argtypes = args
+        built = L.pf_build_id().decode()
+        want = source_id()
+        if built != want:
+            raise ImportError("stale libpf.so: built from sources %s, the sources here are %s; "
+                              "rebuild with __graft_entry__.build()" % (built, want))
         _lib = L
     return _lib
 
@@ -190,7 +206,7 @@ def check(code, where):
 
 
 def make_params(n, model=None, method="ark436l", precision="fp64", adaptive=False,
-                dt0=1e-2, rtol=1e-6, atol=1e-9, dt_min=0.0, dt_max=1e300, max_rejects=10):
+                dt0=1e-2, rtol=1e-6, atol=1e-9, dt_min=0.0, dt_max=1e300, max_rejects=10, norm_space=0):
     """Build a Params struct; ``n`` is an int (cubic) or (nx, ny, nz)."""
     p = Params()
     check(lib().pf_default_params(ctypes.byref(p)), "pf_default_params")
@@ -217,4 +233,5 @@ def make_params(n, model=None, method="ark436l", precision="fp64", adaptive=Fals
     p.dt0, p.rtol, p.atol = float(dt0), float(rtol), float(atol)
     p.dt_min, p.dt_max = float(dt_min), float(dt_max)
     p.max_rejects = int(max_rejects)
+    p.norm_space = int(norm_space)
     return p

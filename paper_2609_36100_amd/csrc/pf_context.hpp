@@ -194,10 +194,12 @@ struct pf_ctx {
   // F^I buffer, E into the unused F^I_1 buffer); the update reads y, U, E, F^E_s
   bool fold_last = false;
   int mixed = 0;
+  bool norm_real = false;  // WRMS of the error in real space (norm_space = 1)
 
   bool owns = true;  // false for views whose buffers belong to an ensemble
   pf::cx<double>* y = nullptr;
   pf::cx<double>* ynew = nullptr;
+  pf::cx<double>* ycopy = nullptr;  // norm_space = 1: the previous state, transformed back
   pf::cx<double>* FI[6] = {nullptr};
   void* FE[6] = {nullptr};  // cx<double> (FP64) or cx<float> (mixed)
   void* scratch = nullptr;  // T1 (4 fields) | T3 (3 fields) of the FFT precision
@@ -227,6 +229,7 @@ struct pf_ctx {
   int64_t ws_bytes = 0;
   double t = 0.0;
   double dt_next = 0.0;
+  bool prev_rejected = false;  // the last attempt was rejected (caps the next proposal's growth)
   bool have_state = false;
   pf_stats st;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -238,4 +241,7 @@ namespace pf {
 void ctx_setup(pf_ctx* c, const pf_params* p, hipStream_t stream);   // geometry, model, tables
 void make_twiddles64(int n, cx<double>* host);
 void make_twiddles32(int n, cx<float>* host);
+// mass, volume fraction, threshold fraction and (want_F) total free energy of
+// the context's current state; F is NaN without want_F
+pf_status ctx_diagnostics(pf_ctx* c, bool want_F, double out[4]);
 }  // namespace pf

@@ -59,11 +59,15 @@ struct EMemb {
 };
 
 // per-member integration state (device, mirrored on the host between calls)
+// dt is the next attempt (the proposal dt_next capped by dt_max and clipped to
+// t_final); dt_next is the controller's proposal itself, kept so that a later
+// advance to a larger t_final resumes from it.
 struct EState {
-  double t, dt, tf, err, dt_last;
+  double t, dt, tf, err, dt_last, dt_next;
   double rtol, atol, dt0, dt_min, dt_max;
   long long steps, attempts, rejects, n_rhs;
-  int cur, done, rejrow, adaptive, max_rejects, pad;
+  int cur, done, rejrow, adaptive, max_rejects;
+  int prevrej;  // the last attempt was rejected (caps the next proposal's growth)
 };
 
 struct StageCoef {
@@ -360,7 +364,8 @@ __global__ void __launch_bounds__(256) kb_control(const EMemb<T, TE>* mem, EStat
   double nxt;
   if (s.adaptive) {
     ok = finite && err <= 1.0;
-    nxt = fmax(ctrl_factor(s.dt, err, q, !ok), s.dt_min);
+    nxt = fmax(ctrl_factor(s.dt, err, q, ok && s.prevrej != 0), s.dt_min);
+    s.prevrej = ok ? 0 : 1;
   } else {
     ok = finite;
     nxt = s.dt0;
@@ -385,7 +390,9 @@ __global__ void __launch_bounds__(256) kb_control(const EMemb<T, TE>* mem, EStat
   } else if (s.t >= s.tf * (1.0 - 1e-15)) {
     s.done = 1;
   }
-  // next attempt: the controller's proposal (or dt0), capped and clipped to t_final
+  // next attempt: the controller's proposal (or dt0), capped and clipped to
+  // t_final; the proposal itself is kept for a later advance
+  s.dt_next = nxt;
   s.dt = fmin(fmin(nxt, s.dt_max), s.tf - s.t);
   st[m] = s;
 }
@@ -658,6 +665,7 @@ pf_status pf_ensemble_init(int32_t n, const pf_params* per_member, void* stream,
       return PF_ERR_ARG;
     if (p.precision != PF_FP64 && p.precision != PF_MIXED) return PF_ERR_ARG;
     if (p.dx <= 0.0 || (p.adaptive && (p.rtol < 0.0 || p.atol <= 0.0))) return PF_ERR_ARG;
+    if (p.norm_space != 0) return PF_ERR_ARG;  // ensembles take the k-space norm only
   }
   int ndev = 0;  // no usable device: a HIP error, before any allocation
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return PF_ERR_HIP;
@@ -737,9 +745,9 @@ pf_status pf_ensemble_init(int32_t n, const pf_params* per_member, void* stream,
       if (s == PF_OK) s = ens_alloc(E, &v->FE[i], fe);
     }
     if (s == PF_OK) s = ens_alloc(E, &v->scratch, v->scratch_bytes);
-    if (s == PF_OK) s = ens_alloc(E, (void**)&v->partial, sizeof(double) * 2 * v->nblk_red);
-    if (s == PF_OK) s = ens_alloc(E, (void**)&v->red, sizeof(double) * 2);
-    if (s == PF_OK && hipHostMalloc((void**)&v->host_red, sizeof(double) * 2, 0) != hipSuccess) s = PF_ERR_OOM;
+    if (s == PF_OK) s = ens_alloc(E, (void**)&v->partial, sizeof(double) * 4 * v->nblk_red);
+    if (s == PF_OK) s = ens_alloc(E, (void**)&v->red, sizeof(double) * 8);
+    if (s == PF_OK && hipHostMalloc((void**)&v->host_red, sizeof(double) * 8, 0) != hipSuccess) s = PF_ERR_OOM;
     if (s != PF_OK) break;
     const int N = g.nz;
     v->tw64[0] = v->tw64[1] = v->tw64[3] = E->tw64[N].first;
@@ -758,6 +766,7 @@ pf_status pf_ensemble_init(int32_t n, const pf_params* per_member, void* stream,
       std::memset(&x, 0, sizeof(x));
       const pf_params& p = per_member[m];
       x.dt = p.dt0;
+      x.dt_next = p.dt0;
       x.rtol = p.rtol;
       x.atol = p.atol;
       x.dt0 = p.dt0;
@@ -819,8 +828,10 @@ pf_status pf_ensemble_set_state(pf_ens* E, int32_t m, const double* c, const dou
   EState& x = E->st_host[m];
   x.t = t0;
   x.dt = E->prm[m].dt0;
+  x.dt_next = E->prm[m].dt0;
   x.steps = x.attempts = x.rejects = x.n_rhs = 0;
   x.rejrow = 0;
+  x.prevrej = 0;
   x.done = 1;
   return PF_OK;
 }
@@ -846,6 +857,13 @@ pf_status pf_ensemble_diagnostics(pf_ens* E, int32_t m, double* mass, double* vf
   return pf_diagnostics(v, mass, vf, vf_thr);
 }
 
+pf_status pf_ensemble_free_energy(pf_ens* E, int32_t m, double* F) {
+  pf_ctx* v;
+  pf_status s = view_for(E, m, &v);
+  if (s != PF_OK) return s;
+  return pf_free_energy(v, F);
+}
+
 int64_t pf_ensemble_kspace_pitch(const pf_ens* E, int32_t m) {
   if (!E || m < 0 || m >= E->M) return 0;
   return E->views[m]->g.P;
@@ -858,7 +876,7 @@ pf_status pf_ensemble_advance(pf_ens* E, const double* t_final, int32_t max_step
     x.tf = t_final[m];
     x.rejrow = 0;
     x.done = (x.t >= x.tf * (1.0 - 1e-15)) ? 1 : 0;
-    if (!x.done) x.dt = std::min(std::min(x.dt, x.dt_max), x.tf - x.t);
+    if (!x.done) x.dt = std::min(std::min(x.dt_next, x.dt_max), x.tf - x.t);
   }
   PF_HIP(hipMemcpyAsync(E->st_dev, E->st_host, sizeof(EState) * E->M, hipMemcpyHostToDevice, E->stream));
   if (!E->exec) {
@@ -901,9 +919,18 @@ pf_status pf_ensemble_advance(pf_ens* E, const double* t_final, int32_t max_step
       o.n_rhs = x.n_rhs;
       o.t = x.t;
       o.dt_last = x.dt_last;
-      o.dt_next = x.dt;
+      o.dt_next = x.dt_next;
       o.err_last = x.err;
       o.elapsed_ms = ms;
+      o.mass = o.F = o.vf = o.vf_threshold = NAN;
+      pf_ctx* v = nullptr;
+      double d[4];
+      if (view_for(E, m, &v) == PF_OK && v->have_state && ctx_diagnostics(v, true, d) == PF_OK) {
+        o.mass = d[0];
+        o.vf = d[1];
+        o.vf_threshold = d[2];
+        o.F = d[3];
+      }
     }
   }
   return status;

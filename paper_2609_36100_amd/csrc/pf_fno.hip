@@ -425,10 +425,12 @@ __global__ void __launch_bounds__(256) k_to_bf16(const float* __restrict__ src, 
   dst[i] = c < cols ? f2bf(src[r * sr + c * sc]) : (u16)0;
 }
 
-// new_state[f][p] = state[f][p] + scale[f] * out[p][f]  (f64 planar state)
-__global__ void __launch_bounds__(256) k_apply(const double* __restrict__ st, const float* __restrict__ out,
+// new_state[f][p] = state[f][p] + scale[f] * out[p][f]  (f64 planar state).
+// st and res may be the same array (in-place advance): each element is read
+// and then written by the same thread, so neither carries __restrict__.
+__global__ void __launch_bounds__(256) k_apply(const double* st, const float* __restrict__ out,
                                                const float* __restrict__ scale, long long P, int co,
-                                               double* __restrict__ res, double* __restrict__ part) {
+                                               double* res, double* __restrict__ part) {
   __shared__ double sh[4];
   const long long p = blockIdx.x * 256LL + threadIdx.x;
   double dc = 0.0;
@@ -877,6 +879,35 @@ pf_status pf_fno_get_grad(pf_fno* F, float* host) {
   return PF_OK;
 }
 
+pf_status pf_fno_load(pf_fno* F, const void* host, size_t bytes) {
+  if (!F || !host) return PF_ERR_ARG;
+  const size_t np = (size_t)F->nparams;
+  if (bytes == 4 * np) return pf_fno_set_params(F, (const float*)host);
+  if (bytes != 2 * np) return PF_ERR_ARG;
+  // bfloat16 -> float32 is exact (the upper half of the float's bits)
+  std::vector<float> w(np);
+  const u16* h = (const u16*)host;
+  for (size_t i = 0; i < np; ++i) w[i] = bf2f(h[i]);
+  return pf_fno_set_params(F, w.data());
+}
+pf_status pf_fno_train_step(pf_fno* F, const float* x, const float* y, int32_t batch, float lr, float* loss) {
+  if (!F || !x || !y || batch < 1 || !(lr > 0.f) || !std::isfinite(lr)) return PF_ERR_ARG;
+  pf_status s = pf_fno_zero_grad(F);
+  if (s != PF_OK) return s;
+  const size_t per = (size_t)F->cfg.cin * (size_t)F->P;
+  double tot = 0.0;
+  for (int b = 0; b < batch; ++b) {
+    double l = 0.0;
+    s = pf_fno_grad(F, x + b * per, y + b * per, &l);
+    if (s != PF_OK) return s;
+    tot += l;
+  }
+  s = pf_fno_adam_step(F, lr, 0.9f, 0.999f, 1e-8f, 1.0f / (float)batch);
+  if (s != PF_OK) return s;
+  FH(hipStreamSynchronize(F->stream));
+  if (loss) *loss = (float)(tot / batch);
+  return PF_OK;
+}
 pf_status pf_fno_zero_grad(pf_fno* F) {
   if (!F) return PF_ERR_ARG;
   FH(hipMemsetAsync(F->gr, 0, 4 * F->nparams, F->stream));

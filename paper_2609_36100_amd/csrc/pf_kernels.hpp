@@ -1136,6 +1136,10 @@ struct FinArgs {
   const cx<double>* E;
   double rtol, atol, sc;  // sc = 1/sqrt(N^3)
   double* partial;        // [2 * gridDim.x]: sum of squares, non-finite count
+  // non-null: the error estimate is also stored here (it may be E or FI[0]:
+  // each element is read before it is written, by the same thread), for a
+  // norm taken in real space
+  cx<double>* err_out;
 };
 
 template <typename TE>
@@ -1178,6 +1182,7 @@ __global__ void __launch_bounds__(256) k_finalize(FinArgs<TE> fa, Geo g, ModelK 
     const cx<double> yn = (fa.U ? fa.U[idx] : y0) + inc;
     fa.ynew[idx] = yn;
     if (!isfinite(yn.re) || !isfinite(yn.im)) bad += 1.0;
+    if (fa.err_out) fa.err_out[idx] = err;
     if (fa.want_err) {
       const double mult = (x == 0 || 2 * (int)x == g.nx) ? 1.0 : 2.0;
       const double ay = sqrt(y0.re * y0.re + y0.im * y0.im) * fa.sc;
@@ -1214,22 +1219,122 @@ __global__ void __launch_bounds__(256) k_reduce_pairs(const double* partial, int
   }
 }
 
-// Volume fraction partial sums over real fields [4][N] (c, eta_1..3).
-__global__ void __launch_bounds__(256) k_vf_partial(const double* u, long long npts, double* partial) {
+// Real-space WRMS partial sums (Eqs. wrms_norm, wrms_weights applied point by
+// point): sum_i (e_i / (rtol |y_i| + atol))^2 over n values of the error e and
+// the previous state y, one value per block.
+__global__ void __launch_bounds__(256) k_wrms_real(const double* e, const double* y, long long n, double rtol,
+                                                   double atol, double* partial) {
   __shared__ double sh[16];
-  double hs = 0.0, cnt = 0.0;
+  double acc = 0.0;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    const double w = e[i] / (rtol * fabs(y[i]) + atol);
+    acc += w * w;
+  }
+  acc = block_sum(acc, sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = acc;
+}
+
+// Sums n partial tuples of nv values (nv <= 4) in a fixed order into out[0..nv).
+__global__ void __launch_bounds__(256) k_reduce_tuples(const double* partial, int n, int nv, double* out) {
+  __shared__ double sh[16];
+  for (int v = 0; v < nv; ++v) {
+    double a = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) a += partial[nv * i + v];
+    a = block_sum(a, sh);
+    if (threadIdx.x == 0) out[v] = a;
+  }
+}
+
+// Real-space diagnostics over the fields u = [4][N] (c, eta_1..3), per block:
+// sum of H = sum_v h(eta_v) (volume fraction), count of points with
+// max_v eta_v > 1/2, and sum of the bulk free-energy density
+// f = W (c - c_m)^2 (1 - H) + W (c - c_p)^2 H + w sum_v eta_v^2 (1 - eta_v)^2.
+// With theta_out set, eta_v is replaced by theta_v = h(eta_v) in place (each
+// point is read, then written, by one thread).
+__global__ void __launch_bounds__(256) k_diag_real(double* u, long long npts, ModelK m, int theta_out,
+                                                   double* partial) {
+  __shared__ double sh[16];
+  double hs = 0.0, cnt = 0.0, fb = 0.0;
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < npts;
        i += (long long)gridDim.x * blockDim.x) {
+    const double c = u[i];
     const double e1 = u[npts + i], e2 = u[2 * npts + i], e3 = u[3 * npts + i];
-    hs += hfun(e1) + hfun(e2) + hfun(e3);
-    const double mx = fmax(e1, fmax(e2, e3));
-    cnt += mx > 0.5 ? 1.0 : 0.0;
+    const double h1 = hfun(e1), h2 = hfun(e2), h3 = hfun(e3);
+    const double H = h1 + h2 + h3;
+    hs += H;
+    cnt += fmax(e1, fmax(e2, e3)) > 0.5 ? 1.0 : 0.0;
+    const double dw = e1 * e1 * (1.0 - e1) * (1.0 - e1) + e2 * e2 * (1.0 - e2) * (1.0 - e2) +
+                      e3 * e3 * (1.0 - e3) * (1.0 - e3);
+    fb += m.W * (c - m.cm) * (c - m.cm) * (1.0 - H) + m.W * (c - m.cp) * (c - m.cp) * H + m.w * dw;
+    if (theta_out) {
+      u[npts + i] = h1;
+      u[2 * npts + i] = h2;
+      u[3 * npts + i] = h3;
+    }
   }
   hs = block_sum(hs, sh);
   cnt = block_sum(cnt, sh);
+  fb = block_sum(fb, sh);
   if (threadIdx.x == 0) {
-    partial[2 * blockIdx.x] = hs;
-    partial[2 * blockIdx.x + 1] = cnt;
+    partial[3 * blockIdx.x] = hs;
+    partial[3 * blockIdx.x + 1] = cnt;
+    partial[3 * blockIdx.x + 2] = fb;
+  }
+}
+
+// Reciprocal-space energy sums over the half spectrum, each mode counted with
+// its multiplicity m(k) (1 for kx = 0 and the Nyquist plane, else 2), per
+// block: the gradient energy kernel sum m k^2 (kappa_c |c~|^2 + kappa_eta
+// sum_v |eta~_v|^2) of the state y, and the elastic energy kernel
+// sum m sum_vw B_vw(k) Re(th~_v conj th~_w) of th~ = FFT(h(eta)) (3 fields),
+// with B(0) the k = 0 rule.  Both still carry 1 / (2 N^3) and dx^3.
+__global__ void __launch_bounds__(256) k_energy_kspace(const cx<double>* y, const cx<double>* th, Geo g, ModelK m,
+                                                       double* partial) {
+  __shared__ double sh[16];
+  const long long nrow = (long long)g.nz * g.ny;
+  const long long total = nrow * g.nxh;
+  double gr = 0.0, el = 0.0;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
+       i += (long long)gridDim.x * blockDim.x) {
+    const int x = (int)(i % g.nxh);
+    const long long row = i / g.nxh;
+    const int yy = (int)(row % g.ny), z = (int)(row / g.ny);
+    const long long idx = row * g.P + x;
+    const double kx = x * g.kfx, ky = mode_of(yy, g.ny) * g.kfy, kz = mode_of(z, g.nz) * g.kfz;
+    const double k2 = kx * kx + ky * ky + kz * kz;
+    const double mult = (x == 0 || 2 * x == g.nx) ? 1.0 : 2.0;
+    const cx<double> cc = y[idx];
+    double eta2 = 0.0;
+#pragma unroll
+    for (int v = 0; v < 3; ++v) {
+      const cx<double> e = y[(1 + v) * g.fs + idx];
+      eta2 += e.re * e.re + e.im * e.im;
+    }
+    gr += mult * k2 * (m.kc * (cc.re * cc.re + cc.im * cc.im) + m.ke * eta2);
+    cx<double> t[3], e[3];
+#pragma unroll
+    for (int v = 0; v < 3; ++v) t[v] = th[v * g.fs + idx];
+    if (x == 0 && yy == 0 && z == 0) {
+#pragma unroll
+      for (int v = 0; v < 3; ++v) {
+        e[v] = mk(0.0, 0.0);
+#pragma unroll
+        for (int w = 0; w < 3; ++w) e[v] = e[v] + m.B0[v][w] * t[w];
+      }
+    } else {
+      elastic_apply<double>(m, kx, ky, kz, t, e);
+    }
+    double q = 0.0;
+#pragma unroll
+    for (int v = 0; v < 3; ++v) q += e[v].re * t[v].re + e[v].im * t[v].im;
+    el += mult * q;
+  }
+  gr = block_sum(gr, sh);
+  el = block_sum(el, sh);
+  if (threadIdx.x == 0) {
+    partial[2 * blockIdx.x] = gr;
+    partial[2 * blockIdx.x + 1] = el;
   }
 }
 

@@ -503,6 +503,7 @@ static pf_status stages_and_finalize(pf_ctx* c, double dt, int* n_rhs) {
   fa.atol = c->p.atol;
   fa.sc = 1.0 / std::sqrt((double)c->g.nx * c->g.ny * c->g.nz);
   fa.partial = c->partial;
+  fa.err_out = (c->norm_real && tb.has_emb) ? c->FI[0] : nullptr;
   // y read + ynew write (4 complex FP64 fields each)
   double b_fin = 2.0 * 4 * c->g.nz * (double)c->g.ny * c->g.nxh * sizeof(cx<double>);
   if (fa.U) b_fin += 2.0 * 4 * c->g.nz * (double)c->g.ny * c->g.nxh * sizeof(cx<double>);  // U and E
@@ -519,6 +520,11 @@ static pf_status stages_and_finalize(pf_ctx* c, double dt, int* n_rhs) {
   return PF_OK;
 }
 
+// Elementary I-controller (the paper leaves the formula to the integration
+// library): dt * min(5, max(0.2, 0.9 err^(-1/(q+1)))), 0.25 dt after a
+// non-finite attempt; `after_reject` (this attempt accepted, the previous one
+// rejected) caps the factor at 1, the facmax = 1 rule of Hairer, Norsett and
+// Wanner right after a rejection.
 static double controller(double dt, double err, int q, bool after_reject) {
   if (!std::isfinite(err)) return 0.25 * dt;
   double fac;
@@ -573,6 +579,7 @@ void ctx_setup(pf_ctx* c, const pf_params* p, hipStream_t stream) {
   if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device) == hipSuccess && ncu > 0)
     c->num_cu = ncu;
   c->mixed = p->precision == PF_MIXED;
+  c->norm_real = p->norm_space == 1;
   Geo& g = c->g;
   g.nx = p->nx;
   g.ny = p->ny;
@@ -661,6 +668,11 @@ pf_status pf_bandwidth_probe(int64_t bytes, int32_t reps, void* stream, double* 
   return res;
 }
 
+#ifndef PF_BUILD_ID
+#define PF_BUILD_ID "unversioned"
+#endif
+const char* pf_build_id(void) { return PF_BUILD_ID; }
+
 const char* pf_status_string(pf_status s) {
   switch (s) {
     case PF_OK: return "PF_OK";
@@ -718,6 +730,7 @@ void pf_finalize(pf_ctx* c) {
   }
   hipFree(c->y);
   hipFree(c->ynew);
+  hipFree(c->ycopy);
   for (int i = 0; i < 6; ++i) {
     hipFree(c->FI[i]);
     hipFree(c->FE[i]);
@@ -746,6 +759,7 @@ pf_status pf_init(const pf_params* p, void* stream, pf_ctx** out) {
   if (p->adaptive && !method_embedded(p->method)) return PF_ERR_ARG;
   if (p->adaptive && (p->rtol < 0.0 || p->atol <= 0.0)) return PF_ERR_ARG;
   if (p->mean_strain_mode != 0 && p->mean_strain_mode != 1) return PF_ERR_ARG;
+  if (p->norm_space != 0 && p->norm_space != 1) return PF_ERR_ARG;
   if (!pf_size_supported(p->nx) || !pf_size_supported(p->ny) || !pf_size_supported(p->nz))
     return PF_ERR_UNSUPPORTED_SIZE;
 
@@ -760,18 +774,20 @@ pf_status pf_init(const pf_params* p, void* stream, pf_ctx** out) {
   const size_t fe_bytes = (c->mixed ? sizeof(cx<float>) : sizeof(cx<double>)) * 4 * (size_t)g.fs;
   const size_t tbytes = (c->mixed ? sizeof(cx<float>) : sizeof(cx<double>)) * 7 * (size_t)g.fs;
   const size_t rbytes = sizeof(double) * 4 * (size_t)g.nx * g.ny * g.nz;
-  c->scratch_bytes = std::max(tbytes, rbytes);
+  // a real-space norm holds the error and the previous state (8 real fields)
+  c->scratch_bytes = std::max(tbytes, (c->norm_real ? 2 : 1) * rbytes);
   pf_status s = PF_OK;
   s = dalloc(c, (void**)&c->y, kbytes64);
   if (s == PF_OK) s = dalloc(c, (void**)&c->ynew, kbytes64);
+  if (s == PF_OK && c->norm_real) s = dalloc(c, (void**)&c->ycopy, kbytes64);
   for (int i = 0; i < c->tab.s && s == PF_OK; ++i) {
     if (c->fi_need[i] || i == 0) s = dalloc(c, (void**)&c->FI[i], kbytes64);
     if (s == PF_OK && (c->fe_need[i] || i == 0)) s = dalloc(c, &c->FE[i], fe_bytes);
   }
   if (s == PF_OK) s = dalloc(c, &c->scratch, c->scratch_bytes);
-  if (s == PF_OK) s = dalloc(c, (void**)&c->partial, sizeof(double) * 2 * c->nblk_red);
-  if (s == PF_OK) s = dalloc(c, (void**)&c->red, sizeof(double) * 2);
-  if (s == PF_OK && hipHostMalloc((void**)&c->host_red, sizeof(double) * 2, 0) != hipSuccess) s = PF_ERR_OOM;
+  if (s == PF_OK) s = dalloc(c, (void**)&c->partial, sizeof(double) * 4 * c->nblk_red);
+  if (s == PF_OK) s = dalloc(c, (void**)&c->red, sizeof(double) * 8);
+  if (s == PF_OK && hipHostMalloc((void**)&c->host_red, sizeof(double) * 8, 0) != hipSuccess) s = PF_ERR_OOM;
   if (s == PF_OK) s = upload_twiddles(c, 0, g.nz);
   if (s == PF_OK) s = upload_twiddles(c, 1, g.ny);
   if (s == PF_OK) s = upload_twiddles(c, 2, g.nx / 2);
@@ -847,6 +863,7 @@ pf_status pf_set_state(pf_ctx* c, const double* cfield, const double* eta, int32
   PF_HIP(hipStreamSynchronize(c->stream));
   c->t = t0;
   c->have_state = true;
+  c->prev_rejected = false;
   return PF_OK;
 }
 
@@ -877,6 +894,7 @@ pf_status pf_set_state_hat(pf_ctx* c, const void* y_hat, double t0) {
   PF_HIP(hipStreamSynchronize(c->stream));
   c->t = t0;
   c->have_state = true;
+  c->prev_rejected = false;
   return PF_OK;
 }
 
@@ -910,6 +928,25 @@ pf_status pf_rhs(pf_ctx* c, double t, const void* y_hat, void* fI_hat, void* fE_
   return PF_OK;
 }
 
+// Real-space WRMS of the step's error estimate (norm_space = 1): the error
+// (stored by the finalize in FI[0]) and the previous state are transformed
+// back to real space and weighted point by point; the sum of squares goes to
+// red[2].
+static pf_status wrms_real_space(pf_ctx* c) {
+  const long long n = (long long)c->g.nx * c->g.ny * c->g.nz;
+  double* re = (double*)c->scratch;
+  double* ry = re + 4 * n;
+  pf_status s = inverse3d_fp64(c, c->FI[0], re, 4);
+  if (s != PF_OK) return s;
+  PF_HIP(hipMemcpyAsync(c->ycopy, c->y, sizeof(cx<double>) * 4 * c->g.fs, hipMemcpyDeviceToDevice, c->stream));
+  s = inverse3d_fp64(c, c->ycopy, ry, 4);
+  if (s != PF_OK) return s;
+  k_wrms_real<<<dim3(c->nblk_red), dim3(256), 0, c->stream>>>(re, ry, 4 * n, c->p.rtol, c->p.atol, c->partial);
+  k_reduce_tuples<<<dim3(1), dim3(256), 0, c->stream>>>(c->partial, c->nblk_red, 1, c->red + 2);
+  PF_HIP(hipGetLastError());
+  return PF_OK;
+}
+
 pf_status pf_ark_step(pf_ctx* c, double dt, double* dt_next, double* err_out, int32_t* accepted) {
   if (!c || !(dt > 0.0) || !std::isfinite(dt)) return PF_ERR_ARG;
   if (!c->have_state) return PF_ERR_STATE;
@@ -917,18 +954,24 @@ pf_status pf_ark_step(pf_ctx* c, double dt, double* dt_next, double* err_out, in
   pf_status s = c->mixed ? stages_and_finalize<float, float>(c, dt, &n_rhs)
                          : stages_and_finalize<double, double>(c, dt, &n_rhs);
   if (s != PF_OK) return s;
-  PF_HIP(hipMemcpyAsync(c->host_red, c->red, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  const bool real_norm = c->norm_real && c->tab.has_emb;
+  if (real_norm) {
+    s = wrms_real_space(c);
+    if (s != PF_OK) return s;
+  }
+  PF_HIP(hipMemcpyAsync(c->host_red, c->red, 4 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   PF_HIP(hipStreamSynchronize(c->stream));
   prof_resolve(c);
   const double n3 = (double)c->g.nx * c->g.ny * c->g.nz;
-  double err = c->tab.has_emb ? std::sqrt(c->host_red[0] / (4.0 * n3)) : 0.0;
+  double err = c->tab.has_emb ? std::sqrt(c->host_red[real_norm ? 2 : 0] / (4.0 * n3)) : 0.0;
   const bool finite = c->host_red[1] == 0.0 && std::isfinite(err);
   if (!finite) err = INFINITY;
   bool ok;
   double nxt;
   if (c->p.adaptive) {
     ok = finite && err <= 1.0;
-    nxt = std::max(controller(dt, err, c->tab.emb_order, !ok), c->p.dt_min);
+    nxt = std::max(controller(dt, err, c->tab.emb_order, ok && c->prev_rejected), c->p.dt_min);
+    c->prev_rejected = !ok;
   } else {
     ok = finite;
     nxt = c->p.dt0;
@@ -958,11 +1001,18 @@ pf_status pf_ark_step(pf_ctx* c, double dt, double* dt_next, double* err_out, in
 
 pf_status pf_get_stats(pf_ctx* c, pf_stats* out) {
   if (!c || !out) return PF_ERR_ARG;
-  cx<double> c0;
-  PF_HIP(hipMemcpyAsync(&c0, c->y, sizeof(c0), hipMemcpyDeviceToHost, c->stream));
-  PF_HIP(hipStreamSynchronize(c->stream));
-  c->st.mass = c0.re * c->mk.inv_n3;
   c->st.t = c->t;
+  if (c->have_state) {
+    double d[4];
+    pf_status s = ctx_diagnostics(c, true, d);
+    if (s != PF_OK) return s;
+    c->st.mass = d[0];
+    c->st.vf = d[1];
+    c->st.vf_threshold = d[2];
+    c->st.F = d[3];
+  } else {
+    c->st.mass = c->st.vf = c->st.vf_threshold = c->st.F = NAN;
+  }
   *out = c->st;
   return PF_OK;
 }
@@ -998,23 +1048,87 @@ pf_status pf_advance(pf_ctx* c, double t_final, pf_stats* out) {
   return s;
 }
 
-pf_status pf_diagnostics(pf_ctx* c, double* mass, double* vf, double* vf_thr) {
-  if (!c) return PF_ERR_ARG;
-  const long long n = (long long)c->g.nx * c->g.ny * c->g.nz;
-  PF_HIP(hipMemcpyAsync(c->ynew, c->y, sizeof(cx<double>) * 4 * c->g.fs, hipMemcpyDeviceToDevice, c->stream));
+}  // extern "C"
+
+// Diagnostics of the current state, all in FP64 on the device (the state is
+// FP64 in both precisions): the real-space state from one inverse transform
+// (into the scratch buffer, with the spare state buffer as the transform's
+// intermediate); per-point sums of H, of the threshold count and of the bulk
+// free-energy density; with want_F also the forward transform of
+// theta_v = h(eta_v) and the reciprocal-space gradient and elastic energies.
+// out: mass, vf, vf_threshold, F (F only with want_F).
+namespace pf {
+pf_status ctx_diagnostics(pf_ctx* c, bool want_F, double out[4]) {
+  if (!c->have_state) return PF_ERR_STATE;
+  const Geo& g = c->g;
+  const long long n = (long long)g.nx * g.ny * g.nz;
+  PF_HIP(hipMemcpyAsync(c->ynew, c->y, sizeof(cx<double>) * 4 * g.fs, hipMemcpyDeviceToDevice, c->stream));
   double* stage = (double*)c->scratch;
   pf_status s = inverse3d_fp64(c, c->ynew, stage, 4);
   if (s != PF_OK) return s;
-  k_vf_partial<<<dim3(c->nblk_red), dim3(256), 0, c->stream>>>(stage, n, c->partial);
-  k_reduce_pairs<<<dim3(1), dim3(256), 0, c->stream>>>(c->partial, c->nblk_red, c->red);
+  k_diag_real<<<dim3(c->nblk_red), dim3(256), 0, c->stream>>>(stage, n, c->mk, want_F ? 1 : 0, c->partial);
+  k_reduce_tuples<<<dim3(1), dim3(256), 0, c->stream>>>(c->partial, c->nblk_red, 3, c->red);
   PF_HIP(hipGetLastError());
-  PF_HIP(hipMemcpyAsync(c->host_red, c->red, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  cx<double> th0[3];
+  if (want_F) {
+    // theta~ into the spare state buffer (free again after the inverse transform)
+    s = forward3d_fp64(c, stage + n, c->ynew, 3);
+    if (s != PF_OK) return s;
+    k_energy_kspace<<<dim3(c->nblk_red), dim3(256), 0, c->stream>>>(c->y, c->ynew, g, c->mk, c->partial);
+    k_reduce_tuples<<<dim3(1), dim3(256), 0, c->stream>>>(c->partial, c->nblk_red, 2, c->red + 4);
+    PF_HIP(hipGetLastError());
+    for (int v = 0; v < 3; ++v)
+      PF_HIP(hipMemcpyAsync(&th0[v], c->ynew + v * g.fs, sizeof(cx<double>), hipMemcpyDeviceToHost, c->stream));
+  }
+  PF_HIP(hipMemcpyAsync(c->host_red, c->red, 8 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   cx<double> c0;
   PF_HIP(hipMemcpyAsync(&c0, c->y, sizeof(c0), hipMemcpyDeviceToHost, c->stream));
   PF_HIP(hipStreamSynchronize(c->stream));
-  if (mass) *mass = c0.re / (double)n;
-  if (vf) *vf = c->host_red[0] / (double)n;
-  if (vf_thr) *vf_thr = c->host_red[1] / (double)n;
+  prof_resolve(c);
+  const double* r = c->host_red;
+  out[0] = c0.re / (double)n;
+  out[1] = r[0] / (double)n;
+  out[2] = r[1] / (double)n;
+  out[3] = NAN;
+  if (want_F) {
+    // Eq. 1 on the grid: bulk sum + gradient and elastic energies (Parseval,
+    // 1/(2 N^3)) + the prescribed mean strain's terms, times dx^3
+    const pf_params& p = c->p;
+    double F = r[2] + 0.5 * (r[4] + r[5]) / (double)n;
+    if (p.mean_strain_mode == 0) {
+      const double* eb = p.eps_bar;
+      double ebCeb = 0.0;
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) ebCeb += eb[i] * eb[j] * (i == j ? p.C11 : p.C12);
+      F += 0.5 * (double)n * ebCeb;
+      // hom[v] = -N^3 eps*_v : C : eps_bar
+      for (int v = 0; v < 3; ++v) F += c->mk.hom[v] / (double)n * th0[v].re;
+    }
+    out[3] = F * p.dx * p.dx * p.dx;
+  }
+  return PF_OK;
+}
+}  // namespace pf
+
+extern "C" {
+
+pf_status pf_diagnostics(pf_ctx* c, double* mass, double* vf, double* vf_thr) {
+  if (!c) return PF_ERR_ARG;
+  double out[4];
+  pf_status s = ctx_diagnostics(c, false, out);
+  if (s != PF_OK) return s;
+  if (mass) *mass = out[0];
+  if (vf) *vf = out[1];
+  if (vf_thr) *vf_thr = out[2];
+  return PF_OK;
+}
+
+pf_status pf_free_energy(pf_ctx* c, double* F) {
+  if (!c || !F) return PF_ERR_ARG;
+  double out[4];
+  pf_status s = ctx_diagnostics(c, true, out);
+  if (s != PF_OK) return s;
+  *F = out[3];
   return PF_OK;
 }
 

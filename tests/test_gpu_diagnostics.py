@@ -1,0 +1,184 @@
+"""Device diagnostics against the FP64 oracle: mass, volume fraction, its
+threshold variant and the total free energy F (Eq. 1 on the grid), for single
+grids and ensemble members; the volume fraction at 512^3 against a closed
+form; F non-increasing under IMEX Euler at 128^3 (the gradient-flow
+structure of Eqs. x_gov, phi_gov)."""
+import sys
+
+import numpy as np
+import pytest
+
+import pfinputs
+from oracle import ark as oark
+from oracle import diagnostics as odg
+from oracle import model as om
+from oracle import spectral as osp
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as _t
+    assert _t.cuda.is_available(), "GPU tests need a visible GPU"
+    return _t
+
+
+def _smoothed_state(n, params, seed, n_nuclei, steps=3):
+    """Seeded nuclei, then a few oracle IMEX Euler steps: every field smooth and non-trivial."""
+    c, eta, _ = pfinputs.seeded_nuclei(n, seed, c0=0.16, n_nuclei=n_nuclei, radius=(2, 5), d_min=8.0)
+    m = om.Model((n, n, n), params)
+    y = om.to_kspace(c, eta)
+    for _ in range(steps):
+        y, _, _ = oark.ark_step(y, 0.05, oark.imex_euler(), m.f_explicit, m.implicit_symbol())
+    return m, y
+
+
+def _threshold_slack(m, y):
+    """Points whose largest order parameter lies within 1e-12 of 1/2 (the two
+    FP64 transforms may place them on either side)."""
+    u = osp.irfft3(y, m.shape)
+    return int(np.sum(np.abs(np.max(u[1:4], axis=0) - 0.5) < 1e-12))
+
+
+MODELS = {
+    "default": {},
+    "stress_free": dict(mean_strain_mode=1),
+    "eps_bar_dx": dict(eps_bar=[0.002, -0.001, 0.0015], dx=0.7),
+}
+
+
+@pytest.mark.parametrize("over", sorted(MODELS))
+@pytest.mark.parametrize("n", [32, 64, 128])
+def test_diagnostics_and_free_energy_match_oracle(torch, params, n, over):
+    from paper_2609_36100_amd import Solver
+    _say("diagnostics", n, over)
+    prm = dict(params)
+    prm.update(MODELS[over])
+    m, y = _smoothed_state(n, prm, seed=40 + n, n_nuclei=max(3, n // 8), steps=3 if n <= 64 else 1)
+    mass = odg.mass(y, m.shape)
+    vf, vf_thr = odg.volume_fraction(m, y)
+    F = odg.free_energy(m, y)
+    slack = _threshold_slack(m, y)
+    with Solver(n, prm, method="imex_euler", dt0=0.05) as s:
+        s.set_state_hat(s.kspace_from_numpy(y))
+        d = s.diagnostics()
+        gF = s.free_energy()
+        st = s.stats()
+    print("F", gF, F, "vf", d["vf"], vf, "thr", d["vf_threshold"], vf_thr, flush=True)
+    assert abs(d["mass"] - mass) <= 1e-13 * abs(mass)
+    assert abs(d["vf"] - vf) <= 1e-12 * max(abs(vf), 1e-300)
+    assert abs(d["vf_threshold"] - vf_thr) * n ** 3 <= slack + 1e-6
+    assert abs(gF - F) <= 1e-10 * abs(F)
+    # the stats carry the same values
+    assert st["F"] == gF and st["vf"] == d["vf"] and st["mass"] == d["mass"]
+    assert st["vf_threshold"] == d["vf_threshold"]
+
+
+def test_free_energy_parts_each_matter(torch, params):
+    """F moves with each of its parts: a state whose bulk, gradient and elastic
+    energies are all non-zero, compared term by term through parameter
+    changes that scale one part at a time (kappa, stiffness, W)."""
+    from paper_2609_36100_amd import Solver
+    _say("free energy parts")
+    n = 32
+    vals = {}
+    for name, over in (("base", {}), ("kappa", dict(kappa_c=3.0, kappa_eta=2.0)),
+                       ("stiff", dict(C11=500.0, C12=300.0, C44=240.0)), ("W", dict(W=2.0, w=0.5))):
+        prm = dict(params)
+        prm.update(over)
+        m, y = _smoothed_state(n, params, seed=77, n_nuclei=4)
+        m = om.Model((n, n, n), prm)
+        with Solver(n, prm, method="imex_euler", dt0=0.05) as s:
+            s.set_state_hat(s.kspace_from_numpy(y))
+            vals[name] = (s.free_energy(), odg.free_energy(m, y))
+    for name, (g, o) in vals.items():
+        assert abs(g - o) <= 1e-10 * abs(o), (name, g, o)
+    assert len({round(v[1], 6) for v in vals.values()}) == 4
+
+
+def test_volume_fraction_at_512_closed_form(torch, params):
+    """512^3, fields built on the device: eta_1 = 1/2 + A cos(2 pi x/N + 0.1)
+    (mean of h exactly 1/2), eta_2 = a + b cos(2 pi y/N) (mean h(a) + h''(a) b^2/4
+    + h''''(a) b^4/64), eta_3 = 0, c = 0.16 + 0.01 cos(2 pi z/N) (mean 0.16).
+    The threshold fraction counts the x columns with cos(2 pi x/N + 0.1) > 0."""
+    from paper_2609_36100_amd import Solver
+    _say("vf 512^3 closed form")
+    n = 512
+    A, a, b = 0.3, 0.2, 0.1
+    th = 2 * np.pi * torch.arange(n, dtype=torch.float64, device="cuda") / n
+    u = torch.empty((4, n, n, n), dtype=torch.float64, device="cuda")
+    u[0] = (0.16 + 0.01 * torch.cos(th))[:, None, None]
+    u[1] = (0.5 + A * torch.cos(th + 0.1))[None, None, :]
+    u[2] = (a + b * torch.cos(th))[None, :, None]
+    u[3] = 0.0
+    h_a = a ** 3 * (6 * a * a - 15 * a + 10)
+    h2 = 60 * a - 180 * a * a + 120 * a ** 3
+    h4 = 720 * a - 360
+    vf_expect = 0.5 + h_a + h2 * b * b / 4 + h4 * b ** 4 / 64
+    xs = 2 * np.pi * np.arange(n) / n + 0.1
+    thr_expect = float(np.sum(np.cos(xs) > 0)) / n
+    with Solver(n, params, method="imex_euler", dt0=0.05) as s:
+        s.set_state_device(u)
+        del u
+        d = s.diagnostics()
+    print(d, vf_expect, thr_expect, flush=True)
+    assert abs(d["mass"] - 0.16) <= 1e-13
+    assert abs(d["vf"] - vf_expect) <= 1e-12
+    assert d["vf_threshold"] == thr_expect
+
+
+def test_energy_decreases_under_imex_euler_at_128(torch, params):
+    """40 IMEX Euler steps (dt 0.05) of a 128^3 seeded workload: F(t_{n+1}) <=
+    F(t_n) + 1e-12 |F| at every step, F computed on the device; the first and
+    last values against the oracle."""
+    from paper_2609_36100_amd import Solver
+    _say("energy decrease 128^3")
+    n = 128
+    c, eta, _ = pfinputs.seeded_nuclei(n, 1234, c0=0.16, n_nuclei=40, radius=(2, 5), d_min=8.0)
+    m = om.Model((n, n, n), params)
+    Fs = []
+    with Solver(n, params, method="imex_euler", dt0=0.05) as s:
+        s.set_state(c, eta)
+        Fs.append(s.free_energy())
+        for _ in range(40):
+            acc, _, _ = s.step(0.05)
+            assert acc
+            Fs.append(s.free_energy())
+        y_end = s.kspace_to_numpy(s.get_state_hat())
+    F0 = odg.free_energy(m, om.to_kspace(c, eta))
+    assert abs(Fs[0] - F0) <= 1e-10 * abs(F0)
+    assert abs(Fs[-1] - odg.free_energy(m, y_end)) <= 1e-10 * abs(Fs[-1])
+    for k in range(40):
+        assert Fs[k + 1] <= Fs[k] + 1e-12 * abs(Fs[k]), (k, Fs[k], Fs[k + 1])
+    assert Fs[-1] < Fs[0]
+
+
+def test_ensemble_member_diagnostics_match_oracle(torch, params):
+    from paper_2609_36100_amd import Ensemble
+    _say("ensemble diagnostics")
+    sizes = [32, 48, 64]
+    mem = []
+    for i, n in enumerate(sizes):
+        c, eta, _ = pfinputs.seeded_nuclei(n, 900 + i, c0=0.15, n_nuclei=3 + i, radius=(2, 5), d_min=8.0)
+        mem.append((n, c, eta))
+    with Ensemble([dict(n=n, model=params, adaptive=False, dt0=0.1) for n, _, _ in mem]) as E:
+        for m, (n, c, eta) in enumerate(mem):
+            E.set_state(m, c, eta)
+        st = E.advance(0.2)
+        for m, (n, c, eta) in enumerate(mem):
+            mdl = om.Model((n, n, n), params)
+            y = E.get_state_hat(m)
+            d = E.diagnostics(m)
+            vf, vf_thr = odg.volume_fraction(mdl, y)
+            F = odg.free_energy(mdl, y)
+            assert abs(d["vf"] - vf) <= 1e-12 * max(vf, 1e-300)
+            assert abs(d["vf_threshold"] - vf_thr) * n ** 3 <= _threshold_slack(mdl, y) + 1e-6
+            assert abs(d["mass"] - odg.mass(y, mdl.shape)) <= 1e-13
+            assert abs(E.free_energy(m) - F) <= 1e-10 * abs(F)
+            assert abs(st[m]["F"] - F) <= 1e-10 * abs(F) and st[m]["vf"] == d["vf"]

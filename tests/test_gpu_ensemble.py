@@ -59,6 +59,34 @@ def test_fixed_step_ensemble_matches_oracle(torch, params, block_threads):
             assert st[m]["steps"] == [3, 2, 3][m] and st[m]["n_rhs"] == 6 * st[m]["steps"]
 
 
+def test_large_members_match_oracle(torch, params):
+    """The 96^3 and 128^3 members (the largest sizes of the 64-member workload,
+    whose batched tiles differ most from the small members') against the oracle:
+    two fixed ARK4 steps each, FP64 at 1e-10 and the mixed form at its stated
+    1e-5 bound."""
+    from paper_2609_36100_amd import Ensemble
+    _say("ensemble 96^3 + 128^3 vs oracle")
+    mem = _members([96, 128], seed0=880)
+    refs = []
+    for n, c, eta in mem:
+        mdl = om.Model((n, n, n), params)
+        y = om.to_kspace(c, eta)
+        for _ in range(2):
+            y, _, _ = oark.ark_step(y, 0.1, oark.ark436l2sa(), mdl.f_explicit, mdl.implicit_symbol())
+        refs.append(y)
+    for prec, tol in (("fp64", TOL), ("mixed", 1e-5)):
+        with Ensemble([dict(n=n, model=params, adaptive=False, dt0=0.1, precision=prec) for n, _, _ in mem]) as E:
+            for m, (n, c, eta) in enumerate(mem):
+                E.set_state(m, c, eta)
+            st = E.advance(0.2)
+            for m in range(2):
+                assert st[m]["steps"] == 2
+                g = E.get_state_hat(m)
+                for f in range(4):
+                    r = _rel(g[f], refs[m][f])
+                    assert r < tol, (prec, m, f, r)
+
+
 @pytest.mark.parametrize("method,nrhs", [("ark2", 3), ("ark324l", 4)])
 def test_fixed_step_ensemble_lower_order_pairs(torch, params, method, nrhs):
     """Batched members with the second- and third-order pairs match the oracle."""

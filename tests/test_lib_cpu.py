@@ -64,6 +64,7 @@ def test_argument_checks_precede_any_device_work():
     assert init(method=_lib.PF_IMEX_EULER, adaptive=1) == -1      # no embedding to control with
     assert init(method=_lib.PF_ARK2, adaptive=1, atol=0.0) == -1
     assert init(mean_strain_mode=2) == -1
+    assert init(norm_space=2) == -1 and init(norm_space=-1) == -1
     assert init(nx=7) == -4 and init(nz=88) == -4
     # ensembles: cubic supported sizes, one embedded method, one precision
     arr = (_lib.Params * 2)()
@@ -76,6 +77,8 @@ def test_argument_checks_precede_any_device_work():
     assert L.pf_ensemble_init(2, arr, None, ctypes.byref(h)) == -1
     arr[1] = _lib.make_params(48, None, method="ark324l")
     assert L.pf_ensemble_init(2, arr, None, ctypes.byref(h)) == -1          # mixed methods
+    arr[1] = _lib.make_params(48, None, norm_space=1)
+    assert L.pf_ensemble_init(2, arr, None, ctypes.byref(h)) == -1          # k-space norm only
     arr[1] = _lib.make_params(48, None, precision="mixed")
     assert L.pf_ensemble_init(2, arr, None, ctypes.byref(h)) == -1
     # the surrogate's shape limits
@@ -150,3 +153,15 @@ def test_every_bench_mode_has_its_driver():
     src = open(os.path.join(ROOT, "bench.py")).read()
     for mode in ("ensemble", "time_to_t", "fno", "fno_step", "orders", "oracle_timing"):
         assert 'args.mode == "%s"' % mode in src, mode
+
+
+def test_build_id_matches_sources_and_stale_library_is_refused(monkeypatch):
+    """The library carries the hash of the sources it was built from; the
+    binding refuses a library whose hash differs from the sources beside it."""
+    from paper_2609_36100_amd import _lib, build
+    L = _lib.lib()
+    assert L.pf_build_id().decode() == build.source_id()
+    monkeypatch.setattr(_lib, "_lib", None)
+    monkeypatch.setattr(_lib, "source_id", lambda: "0" * 16)
+    with pytest.raises(ImportError, match="stale"):
+        _lib.lib()
