@@ -182,3 +182,36 @@ def test_ensemble_member_diagnostics_match_oracle(torch, params):
             assert abs(d["mass"] - odg.mass(y, mdl.shape)) <= 1e-13
             assert abs(E.free_energy(m) - F) <= 1e-10 * abs(F)
             assert abs(st[m]["F"] - F) <= 1e-10 * abs(F) and st[m]["vf"] == d["vf"]
+
+
+def _vf_fixture():
+    import os
+    rows = []
+    with open(os.path.join(os.path.dirname(__file__), "golden", "vf_curve_twin64.txt")) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            t, vf, thr, mass, F, steps, rej = line.split()
+            rows.append((float(t), float(vf), float(thr), float(mass), float(F), int(steps), int(rej)))
+    return rows
+
+
+def test_volume_fraction_curve_matches_oracle_fixture(torch, params):
+    """The 64^3 twin of the 512^3 workload by adaptive ARK4 (rtol 1e-6): vf(t),
+    the threshold fraction, mass, F and the step counts at t = 0..8 against the
+    oracle's run (tests/golden/vf_curve_twin64.txt, written by the oracle
+    only).  The nuclei dissolve: vf falls from 4.1e-3 to 3.6e-11 by t = 8."""
+    from paper_2609_36100_amd import Solver
+    _say("vf curve 64^3 twin")
+    rows = _vf_fixture()
+    spec, c, eta = pfinputs.config("twin64")
+    vf0 = rows[0][1]
+    with Solver(64, params, method="ark436l", adaptive=True, dt0=0.01, rtol=1e-6, atol=1e-9) as s:
+        s.set_state(c, eta)
+        for t, vf, thr, mass, F, steps, rej in rows[:9]:
+            st = s.advance(t) if t > 0 else s.stats()
+            assert st["steps"] == steps and st["rejects"] == rej, (t, st["steps"], steps)
+            assert abs(st["vf"] - vf) <= 1e-10 * vf0, (t, st["vf"], vf)
+            assert abs(st["vf_threshold"] - thr) <= 2.0 / 64 ** 3, (t, st["vf_threshold"], thr)
+            assert abs(st["mass"] - mass) <= 1e-13
+            assert abs(st["F"] - F) <= 1e-10 * abs(F), (t, st["F"], F)
