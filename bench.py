@@ -153,25 +153,63 @@ def fft_bench(torch, n, reps=3):
                 kernels=tab)
 
 
+def host_cpu():
+    """CPU model and the logical CPUs this process may run on (lscpu, else /proc/cpuinfo)."""
+    import subprocess
+    model = None
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                model = line.split(":", 1)[1].strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    if model is None:
+        try:
+            for line in open("/proc/cpuinfo"):
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+        except OSError:
+            model = platform.processor() or platform.machine()
+    return dict(model=model, logical_cpus_visible=len(os.sched_getaffinity(0)), logical_cpus_host=os.cpu_count())
+
+
 def cpu_baseline(n=128):
-    """The FP64 oracle, as it stands, on one ARK4(3)6L step at n^3 (single thread)."""
+    """The FP64 oracle, as it stands, on one ARK4(3)6L step at n^3: NumPy's FFT on
+    one thread (the value), and SciPy's FFT on every visible core beside it."""
     import numpy as np  # noqa: F401
     import pfinputs
     from oracle import ark as oark
     from oracle import model as om
+    from oracle import spectral as osp
+    host = host_cpu()
     spec, c, eta = pfinputs.config("mixed512", n=n)
     m = om.Model((n, n, n), pfinputs.default_params())
     m.B()  # one-time per-grid setup, not part of a step
     y = om.to_kspace(c, eta)
     L = m.implicit_symbol()
+    osp.set_fft_backend("numpy")
     t0 = time.perf_counter()
     _, _, nexp = oark.ark_step(y, 0.1, oark.ark436l2sa(), m.f_explicit, L)
     wall = time.perf_counter() - t0
+    workers = host["logical_cpus_visible"]
+    try:
+        osp.set_fft_backend("scipy", workers=workers)
+        t1 = time.perf_counter()
+        oark.ark_step(y, 0.1, oark.ark436l2sa(), m.f_explicit, L)
+        wall_all = time.perf_counter() - t1
+    finally:
+        osp.set_fft_backend("numpy")
     return dict(value=round(n ** 3 * nexp / wall / 1e6, 4), unit="Mpts·stages/s", cores=1,
                 kind="oracle",
                 sample="one ARK4(3)6L step (6 stages) of the NumPy FP64 oracle at %d^3, same seeded "
                        "generator with the nucleus count scaled by volume; pocketfft, one thread; "
-                       "%.1f s; host %s" % (n, wall, platform.processor() or platform.machine()))
+                       "%.1f s" % (n, wall),
+                host=host,
+                all_cores=dict(value=round(n ** 3 * nexp / wall_all / 1e6, 4), cores=workers,
+                               sample="the same step with scipy.fft on %d workers (the pointwise and "
+                                      "elastic NumPy work stays on one thread); %.1f s" % (workers, wall_all)))
 
 
 def ensemble_bench(torch, count, t_final, rtol, atol, ref_members, precisions=("fp64", "mixed"),

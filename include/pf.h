@@ -97,6 +97,23 @@ typedef struct {
    *   (the paper applies the test to the change of the fields; two extra
    *   inverse 3D transforms of 4 fields per attempted step, single grids only). */
   int32_t norm_space;
+  /* Inhomogeneous elasticity (Eq. u_gov with the Reuss average of the
+   * phases' stiffness; Methods, "MEUMAPPS C++ and the MEUMAPPS-SS
+   * application": the Hu-Chen iteration; Results, "Improved performance via
+   * time integration approach": its tight 1e-16 and loose 1e-6 tolerances).
+   * 1: local stiffness C(r) = (H S_p + (1 - H) S_m)^-1 between the matrix
+   * stiffness (C11, C12, C44) and the precipitate stiffness (C11p, C12p,
+   * C44p, shared by every variant, cubic in the grid axes), H = sum_v
+   * h(eta_v); mechanical equilibrium by the polarisation iteration with the
+   * reference stiffness (C_m + C_p) / 2, started from its homogeneous
+   * solution at every RHS evaluation and stopped when the largest change of
+   * a strain component is <= el_tol or after el_max_iter updates.  Needs
+   * precision FP64 and mean_strain_mode 0; single grids only.  0 (default):
+   * one stiffness (C11, C12, C44), solved exactly per wavevector. */
+  int32_t elastic_inhom;
+  double C11p, C12p, C44p;
+  double el_tol;
+  int32_t el_max_iter;
 } pf_params;
 
 typedef struct {
@@ -114,6 +131,8 @@ typedef struct {
   double F;            /* total free energy (Eq. 1 on the grid; see pf_free_energy) */
   double vf;           /* precipitate volume fraction: mean of H = sum_v h(eta_v) */
   double vf_threshold; /* fraction of points with max_v eta_v > 1/2 */
+  int64_t el_iterations; /* elastic_inhom: iteration updates over all RHS evaluations */
+  int64_t el_last;       /* elastic_inhom: updates in the last RHS evaluation */
 } pf_stats;
 
 /* Fills p with the defaults of the stand-in model (Methods, "Phase-field

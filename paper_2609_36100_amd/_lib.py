@@ -41,6 +41,10 @@ class Params(ctypes.Structure):
         ("dt_min", ctypes.c_double), ("dt_max", ctypes.c_double),
         ("max_rejects", ctypes.c_int32),
         ("norm_space", ctypes.c_int32),
+        ("elastic_inhom", ctypes.c_int32),
+        ("C11p", ctypes.c_double), ("C12p", ctypes.c_double), ("C44p", ctypes.c_double),
+        ("el_tol", ctypes.c_double),
+        ("el_max_iter", ctypes.c_int32),
     ]
 
 
@@ -69,6 +73,7 @@ class Stats(ctypes.Structure):
         ("err_last", ctypes.c_double), ("mass", ctypes.c_double),
         ("elapsed_ms", ctypes.c_double),
         ("F", ctypes.c_double), ("vf", ctypes.c_double), ("vf_threshold", ctypes.c_double),
+        ("el_iterations", ctypes.c_int64), ("el_last", ctypes.c_int64),
     ]
 
     def as_dict(self):
@@ -227,6 +232,13 @@ def make_params(n, model=None, method="ark436l", precision="fp64", adaptive=Fals
         p.mean_strain_mode = int(model["mean_strain_mode"])
     if "implicit_bulk_c" in model:
         p.implicit_bulk_c = int(model["implicit_bulk_c"])
+    if "C11p" in model:      # a precipitate stiffness selects the inhomogeneous (Reuss) elasticity
+        p.elastic_inhom = 1
+        p.C11p, p.C12p, p.C44p = float(model["C11p"]), float(model["C12p"]), float(model["C44p"])
+    if "el_tol" in model:
+        p.el_tol = float(model["el_tol"])
+    if "el_max_iter" in model:
+        p.el_max_iter = int(model["el_max_iter"])
     p.method = METHODS[method] if isinstance(method, str) else int(method)
     p.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     p.adaptive = 1 if adaptive else 0

@@ -195,6 +195,11 @@ struct pf_ctx {
   bool fold_last = false;
   int mixed = 0;
   bool norm_real = false;  // WRMS of the error in real space (norm_space = 1)
+  bool inhom = false;      // Reuss-averaged stiffness, Hu-Chen iteration (elastic_inhom = 1)
+  pf::cx<double>* E6 = nullptr;  // inhom: six strain / polarisation spectra
+  double* R6 = nullptr;          // inhom: six real strain fields
+  double* elmax = nullptr;       // inhom: largest strain change of the last update
+  double* el_part = nullptr;     // inhom: per-block elastic energy sums
 
   bool owns = true;  // false for views whose buffers belong to an ensemble
   pf::cx<double>* y = nullptr;

@@ -666,6 +666,7 @@ pf_status pf_ensemble_init(int32_t n, const pf_params* per_member, void* stream,
     if (p.precision != PF_FP64 && p.precision != PF_MIXED) return PF_ERR_ARG;
     if (p.dx <= 0.0 || (p.adaptive && (p.rtol < 0.0 || p.atol <= 0.0))) return PF_ERR_ARG;
     if (p.norm_space != 0) return PF_ERR_ARG;  // ensembles take the k-space norm only
+    if (p.elastic_inhom != 0) return PF_ERR_ARG;  // and the homogeneous elasticity
   }
   int ndev = 0;  // no usable device: a HIP error, before any allocation
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return PF_ERR_HIP;

@@ -46,6 +46,12 @@ struct ModelK {
   double C11, C12, C44;
   double hom[3];            // N^3 * (-eps*_v : C : eps_bar), added to e~_v(0)
   double inv_n3;            // 1 / (nx ny nz)
+  // inhomogeneous elasticity (Reuss average between matrix and precipitate)
+  double Sm[3], dS[3];      // matrix compliance (S11, S12, S44; engineering shears), S_p - S_m
+  double C0[3];             // reference stiffness (C_m + C_p) / 2
+  double C0eps[3][3];       // (C0 eps*_v)_ii, [v][i]
+  double eps[3][3];         // eigenstrain diagonals eps*_v, [v][i]
+  double ebar[3];           // prescribed mean strain (diagonal)
 };
 
 __host__ __device__ inline int mode_of(int i, int n) { return (2 * i < n) ? i : i - n; }

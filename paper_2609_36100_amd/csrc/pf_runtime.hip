@@ -19,6 +19,7 @@
 
 #include "../../include/pf.h"
 #include "pf_context.hpp"
+#include "pf_inhom.hpp"
 #include "pf_kernels.hpp"
 
 using namespace pf;
@@ -199,6 +200,33 @@ static void setup_model(pf_ctx* c) {
       for (int i = 0; i < 3; ++i) s += p.eps_bar[i] * m.S[v][i];
     m.hom[v] = -n3 * s;
   }
+  if (p.elastic_inhom) {
+    // cubic compliance from cubic stiffness: S11 = (C11 + C12) / D,
+    // S12 = -C12 / D, D = (C11 - C12)(C11 + 2 C12); S44 = 1 / C44
+    auto comp = [](double c11, double c12, double c44, double s[3]) {
+      const double d = (c11 - c12) * (c11 + 2.0 * c12);
+      s[0] = (c11 + c12) / d;
+      s[1] = -c12 / d;
+      s[2] = 1.0 / c44;
+    };
+    double sm[3], sp[3];
+    comp(p.C11, p.C12, p.C44, sm);
+    comp(p.C11p, p.C12p, p.C44p, sp);
+    for (int i = 0; i < 3; ++i) {
+      m.Sm[i] = sm[i];
+      m.dS[i] = sp[i] - sm[i];
+    }
+    m.C0[0] = 0.5 * (p.C11 + p.C11p);
+    m.C0[1] = 0.5 * (p.C12 + p.C12p);
+    m.C0[2] = 0.5 * (p.C44 + p.C44p);
+    for (int v = 0; v < 3; ++v)
+      for (int i = 0; i < 3; ++i) {
+        const double* e = p.eps_star[v];
+        m.eps[v][i] = e[i];
+        m.C0eps[v][i] = m.C0[0] * e[i] + m.C0[1] * (e[(i + 1) % 3] + e[(i + 2) % 3]);
+      }
+    for (int i = 0; i < 3; ++i) m.ebar[i] = p.eps_bar[i];
+  }
 }
 
 // ---- launchers ----------------------------------------------------------------
@@ -344,11 +372,12 @@ static bool launch_xpass_c2r(pf_ctx* c, const cx<double>* in, double* re, int nf
 // ---- per-kernel-class timing --------------------------------------------------
 enum KClass {
   KC_STAGE = 0, KC_YFFT, KC_THETA, KC_ELASTIC, KC_DRIVE, KC_ZFWD_AC, KC_FINAL,
-  KC_XR2C, KC_XC2R, KC_ZFFT, KC_COUNT
+  KC_XR2C, KC_XC2R, KC_ZFFT, KC_EL_K, KC_EL_TAU, KC_EL_STRAIN, KC_EL_DRIVE, KC_COUNT
 };
 static const char* const kc_names[KC_COUNT] = {
     "stage_invz", "ypass", "xpass_theta", "zpass_elastic", "xpass_drive",
-    "zpass_fwd_ac", "finalize", "xpass_r2c", "xpass_c2r", "zpass"};
+    "zpass_fwd_ac", "finalize", "xpass_r2c", "xpass_c2r", "zpass",
+    "el_kspace", "el_tau", "el_strain", "el_drive"};
 
 static void prof_begin(pf_ctx* c) {
   if (!c->prof_on) return;
@@ -385,6 +414,129 @@ static void prof_resolve(pf_ctx* c) {
   c->prof_used = 0;
 }
 
+// ---- inhomogeneous elasticity: the Hu-Chen iteration ---------------------------
+template <int K>
+static bool launch_el_rows(pf_ctx* c, const cx<double>* T1, cx<double>* out, double* mx) {
+  const Geo& g = c->g;
+  return row_dispatch(g.nx / 2, [&](auto MC) {
+    constexpr int M = decltype(MC)::value;
+    constexpr int RB = rb_of(M);
+    const int nb = (g.nz * g.ny + RB - 1) / RB;
+    const dim3 blk(RowGeo<M, RB>::THREADS);
+    const cx<double>* twN = tw<double>(c, 3);
+    const cx<double>* twM = tw<double>(c, 2);
+    if constexpr (K == 0)
+      k_el_strain<M, RB><<<nb, blk, 0, c->stream>>>(c->E6, c->R6, g, twN, twM, mx);
+    else if constexpr (K == 1)
+      k_el_tau<M, RB><<<nb, blk, 0, c->stream>>>(T1, c->R6, c->E6, g, c->mk, twN, twM);
+    else if constexpr (K == 2)
+      k_el_drive<M, RB><<<nb, blk, 0, c->stream>>>(T1, c->R6, out, g, c->mk, twN, twM);
+    else
+      k_el_energy<M, RB><<<nb, blk, 0, c->stream>>>(T1, c->R6, g, c->mk, twN, twM, c->el_part);
+  });
+}
+static int el_row_blocks(const pf_ctx* c) {
+  int nb = 0;
+  row_dispatch(c->g.nx / 2, [&](auto MC) {
+    constexpr int M = decltype(MC)::value;
+    nb = (c->g.nz * c->g.ny + rb_of(M) - 1) / rb_of(M);
+  });
+  return nb;
+}
+
+// Strain of the periodic displacement at mechanical equilibrium for the order
+// parameters in T1 (the state after its inverse z and y transforms): the
+// start from theta~, then updates until the largest change of a strain
+// component is <= el_tol or el_max_iter updates; the result is in R6.  With
+// FE0, the explicit Cahn-Hilliard term (from H~, which the start has at hand)
+// goes into FE0 (added with `accumulate`).  T3 and E6 are used as temporaries.
+static pf_status el_solve(pf_ctx* c, cx<double>* T1, cx<double>* FE0, int accumulate) {
+  const Geo& g = c->g;
+  cx<double>* T3 = T1 + 4 * g.fs;
+  const double nv = (double)g.nz * g.ny * g.nxh;
+  const double fk = nv * sizeof(cx<double>), fr = (double)g.nx * g.ny * g.nz * sizeof(double);
+  const long long modes = (long long)g.nz * g.ny * g.nxh;
+  const int kgrid = (int)std::min<long long>((modes + 255) / 256, 16384);
+  const double s = c->mk.inv_n3;
+  bool ok = true;
+  auto back = [&](double* mx) {  // E6 spectra -> R6 real strain
+    prof_begin(c);
+    ok = ok && launch_colfft<double, +1, 2>(c, c->E6, c->E6, 6, s);
+    prof_end(c, KC_ZFFT, 12 * fk);
+    prof_begin(c);
+    ok = ok && launch_colfft<double, +1, 1>(c, c->E6, c->E6, 6, 1.0);
+    prof_end(c, KC_YFFT, 12 * fk);
+    prof_begin(c);
+    ok = ok && launch_el_rows<0>(c, nullptr, nullptr, mx);
+    prof_end(c, KC_EL_STRAIN, 6 * fk + (mx ? 12 : 6) * fr);
+  };
+  prof_begin(c);
+  ok = ok && launch_xpass_theta<double>(c, T1, T3);
+  prof_end(c, KC_THETA, 6 * fk);
+  prof_begin(c);
+  ok = ok && launch_colfft<double, -1, 1>(c, T3, T3, 3, 1.0);
+  prof_end(c, KC_YFFT, 6 * fk);
+  prof_begin(c);
+  ok = ok && launch_colfft<double, -1, 2>(c, T3, T3, 3, 1.0);
+  prof_end(c, KC_ZFFT, 6 * fk);
+  prof_begin(c);
+  k_el_start<<<kgrid, 256, 0, c->stream>>>(T3, c->E6, FE0, accumulate, g, c->mk);
+  prof_end(c, KC_EL_K, (9.0 + (FE0 ? (accumulate ? 2 : 1) : 0)) * fk);
+  back(nullptr);
+  int it = 0;
+  while (ok && it < c->p.el_max_iter) {
+    prof_begin(c);
+    ok = ok && launch_el_rows<1>(c, T1, nullptr, nullptr);
+    prof_end(c, KC_EL_TAU, 9 * fk + 6 * fr);  // eta rows, the strain (normal parts re-read from cache)
+    prof_begin(c);
+    ok = ok && launch_colfft<double, -1, 1>(c, c->E6, c->E6, 6, 1.0);
+    prof_end(c, KC_YFFT, 12 * fk);
+    prof_begin(c);
+    ok = ok && launch_colfft<double, -1, 2>(c, c->E6, c->E6, 6, 1.0);
+    prof_end(c, KC_ZFFT, 12 * fk);
+    prof_begin(c);
+    k_el_gamma<<<kgrid, 256, 0, c->stream>>>(c->E6, g, c->mk);
+    prof_end(c, KC_EL_K, 12 * fk);
+    k_el_zero<<<1, 1, 0, c->stream>>>(c->elmax);
+    back(c->elmax);
+    ++it;
+    if (!ok) break;
+    PF_HIP(hipMemcpyAsync(&c->host_red[6], c->elmax, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    PF_HIP(hipStreamSynchronize(c->stream));
+    if (c->host_red[6] <= c->p.el_tol) break;  // a NaN change never stops early
+  }
+  if (!ok) return PF_ERR_UNSUPPORTED_SIZE;
+  if (hipGetLastError() != hipSuccess) return PF_ERR_HIP;
+  c->st.el_iterations += it;
+  c->st.el_last = it;
+  return PF_OK;
+}
+
+// The explicit right-hand side after the state's inverse z and y transforms,
+// with the inhomogeneous elastic force: equilibrium strain, driving forces,
+// forward transforms into FE (fields 1..3; field 0 from the strain's start).
+static pf_status run_rhs_inhom(pf_ctx* c, cx<double>* T1, cx<double>* FE, int accumulate) {
+  const Geo& g = c->g;
+  cx<double>* T3 = T1 + 4 * g.fs;
+  const double nv = (double)g.nz * g.ny * g.nxh;
+  const double fk = nv * sizeof(cx<double>), fr = (double)g.nx * g.ny * g.nz * sizeof(double);
+  pf_status st = el_solve(c, T1, FE, accumulate);
+  if (st != PF_OK) return st;
+  bool ok = true;
+  prof_begin(c);
+  ok = ok && launch_el_rows<2>(c, T1, T3, nullptr);
+  prof_end(c, KC_EL_DRIVE, 7 * fk + 6 * fr);
+  prof_begin(c);
+  ok = ok && launch_colfft<double, -1, 1>(c, T3, T3, 3, 1.0);
+  prof_end(c, KC_YFFT, 6 * fk);
+  prof_begin(c);
+  ok = ok && launch_zpass_fwd_ac<double, double>(c, T3, FE);
+  prof_end(c, KC_ZFWD_AC, 6 * fk);
+  if (!ok) return PF_ERR_UNSUPPORTED_SIZE;
+  if (hipGetLastError() != hipSuccess) return PF_ERR_HIP;
+  return PF_OK;
+}
+
 // ---- one stage: combine / implicit solve, then the explicit RHS chain ---------
 template <typename T, typename TE>
 static pf_status run_stage(pf_ctx* c, const StageArgs<TE>& sa, bool need_rhs, cx<TE>* FE_out) {
@@ -412,6 +564,12 @@ static pf_status run_stage(pf_ctx* c, const StageArgs<TE>& sa, bool need_rhs, cx
     prof_begin(c);
     ok = ok && launch_colfft<T, +1, 1>(c, T1, T1, 4, (T)1);
     prof_end(c, KC_YFFT, 8 * fT);
+    if constexpr (std::is_same<T, double>::value && std::is_same<TE, double>::value) {
+      if (c->inhom) {
+        if (!ok) return PF_ERR_UNSUPPORTED_SIZE;
+        return run_rhs_inhom(c, T1, FE_out, acc);
+      }
+    }
     prof_begin(c);
     ok = ok && launch_xpass_theta<T>(c, T1, T3);
     prof_end(c, KC_THETA, 6 * fT);
@@ -580,6 +738,7 @@ void ctx_setup(pf_ctx* c, const pf_params* p, hipStream_t stream) {
     c->num_cu = ncu;
   c->mixed = p->precision == PF_MIXED;
   c->norm_real = p->norm_space == 1;
+  c->inhom = p->elastic_inhom == 1;
   Geo& g = c->g;
   g.nx = p->nx;
   g.ny = p->ny;
@@ -711,6 +870,13 @@ pf_status pf_default_params(pf_params* p) {
   p->dt_min = 0.0;
   p->dt_max = 1e300;
   p->max_rejects = 10;
+  p->norm_space = 0;
+  p->elastic_inhom = 0;
+  p->C11p = p->C11;
+  p->C12p = p->C12;
+  p->C44p = p->C44;
+  p->el_tol = 1e-16;
+  p->el_max_iter = 50;
   return PF_OK;
 }
 
@@ -731,6 +897,10 @@ void pf_finalize(pf_ctx* c) {
   hipFree(c->y);
   hipFree(c->ynew);
   hipFree(c->ycopy);
+  hipFree(c->E6);
+  hipFree(c->R6);
+  hipFree(c->elmax);
+  hipFree(c->el_part);
   for (int i = 0; i < 6; ++i) {
     hipFree(c->FI[i]);
     hipFree(c->FE[i]);
@@ -760,6 +930,16 @@ pf_status pf_init(const pf_params* p, void* stream, pf_ctx** out) {
   if (p->adaptive && (p->rtol < 0.0 || p->atol <= 0.0)) return PF_ERR_ARG;
   if (p->mean_strain_mode != 0 && p->mean_strain_mode != 1) return PF_ERR_ARG;
   if (p->norm_space != 0 && p->norm_space != 1) return PF_ERR_ARG;
+  if (p->elastic_inhom != 0 && p->elastic_inhom != 1) return PF_ERR_ARG;
+  if (p->elastic_inhom) {
+    // stable cubic stiffnesses, FP64, a prescribed mean strain
+    auto stable = [](double c11, double c12, double c44) {
+      return c11 - c12 > 0.0 && c11 + 2.0 * c12 > 0.0 && c44 > 0.0;
+    };
+    if (!stable(p->C11, p->C12, p->C44) || !stable(p->C11p, p->C12p, p->C44p)) return PF_ERR_ARG;
+    if (p->precision != PF_FP64 || p->mean_strain_mode != 0) return PF_ERR_ARG;
+    if (!(p->el_tol >= 0.0) || p->el_max_iter < 0) return PF_ERR_ARG;
+  }
   if (!pf_size_supported(p->nx) || !pf_size_supported(p->ny) || !pf_size_supported(p->nz))
     return PF_ERR_UNSUPPORTED_SIZE;
 
@@ -780,6 +960,10 @@ pf_status pf_init(const pf_params* p, void* stream, pf_ctx** out) {
   s = dalloc(c, (void**)&c->y, kbytes64);
   if (s == PF_OK) s = dalloc(c, (void**)&c->ynew, kbytes64);
   if (s == PF_OK && c->norm_real) s = dalloc(c, (void**)&c->ycopy, kbytes64);
+  if (s == PF_OK && c->inhom) s = dalloc(c, (void**)&c->E6, sizeof(cx<double>) * 6 * (size_t)g.fs);
+  if (s == PF_OK && c->inhom) s = dalloc(c, (void**)&c->R6, sizeof(double) * 6 * (size_t)g.nx * g.ny * g.nz);
+  if (s == PF_OK && c->inhom) s = dalloc(c, (void**)&c->elmax, sizeof(double));
+  if (s == PF_OK && c->inhom) s = dalloc(c, (void**)&c->el_part, sizeof(double) * (size_t)el_row_blocks(c));
   for (int i = 0; i < c->tab.s && s == PF_OK; ++i) {
     if (c->fi_need[i] || i == 0) s = dalloc(c, (void**)&c->FI[i], kbytes64);
     if (s == PF_OK && (c->fe_need[i] || i == 0)) s = dalloc(c, &c->FE[i], fe_bytes);
@@ -1062,6 +1246,23 @@ pf_status ctx_diagnostics(pf_ctx* c, bool want_F, double out[4]) {
   if (!c->have_state) return PF_ERR_STATE;
   const Geo& g = c->g;
   const long long n = (long long)g.nx * g.ny * g.nz;
+  double el_sum = 0.0;
+  if (want_F && c->inhom) {
+    // elastic energy sum_r sigma : (eps_bar + eps_u - eps*) / 2 at the
+    // equilibrium strain of the current state (FP64 contexts only)
+    cx<double>* T1 = (cx<double>*)c->scratch;
+    if (!launch_colfft<double, +1, 2>(c, c->y, T1, 4, c->mk.inv_n3) ||
+        !launch_colfft<double, +1, 1>(c, T1, T1, 4, 1.0))
+      return PF_ERR_UNSUPPORTED_SIZE;
+    pf_status se = el_solve(c, T1, nullptr, 0);
+    if (se != PF_OK) return se;
+    if (!launch_el_rows<3>(c, T1, nullptr, nullptr)) return PF_ERR_UNSUPPORTED_SIZE;
+    k_reduce_tuples<<<dim3(1), dim3(256), 0, c->stream>>>(c->el_part, el_row_blocks(c), 1, c->red + 6);
+    PF_HIP(hipGetLastError());
+    PF_HIP(hipMemcpyAsync(&c->host_red[6], c->red + 6, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    PF_HIP(hipStreamSynchronize(c->stream));
+    el_sum = c->host_red[6];
+  }
   PF_HIP(hipMemcpyAsync(c->ynew, c->y, sizeof(cx<double>) * 4 * g.fs, hipMemcpyDeviceToDevice, c->stream));
   double* stage = (double*)c->scratch;
   pf_status s = inverse3d_fp64(c, c->ynew, stage, 4);
@@ -1094,8 +1295,10 @@ pf_status ctx_diagnostics(pf_ctx* c, bool want_F, double out[4]) {
     // Eq. 1 on the grid: bulk sum + gradient and elastic energies (Parseval,
     // 1/(2 N^3)) + the prescribed mean strain's terms, times dx^3
     const pf_params& p = c->p;
-    double F = r[2] + 0.5 * (r[4] + r[5]) / (double)n;
-    if (p.mean_strain_mode == 0) {
+    double F = r[2] + 0.5 * (r[4] + (c->inhom ? 0.0 : r[5])) / (double)n;
+    if (c->inhom) {
+      F += el_sum;  // includes the mean strain
+    } else if (p.mean_strain_mode == 0) {
       const double* eb = p.eps_bar;
       double ebCeb = 0.0;
       for (int i = 0; i < 3; ++i)

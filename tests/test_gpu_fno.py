@@ -1,6 +1,8 @@
 """FNO surrogate kernels (BF16 MFMA, FP32 accumulate) against the FP64 oracle:
-forward output and every parameter gradient, bound 3e-2 relative L2 (BF16
-activations and weights carry ~4e-3 relative rounding per value)."""
+forward output at 3e-2 relative L2 and every parameter gradient at 1e-2
+(BF16 activations and weights carry ~4e-3 relative rounding per value; on
+zero-mean inputs the gradients measure 4e-5 to 2e-3, the imaginary spectral
+weights 6.3e-3 to 7.9e-3)."""
 import sys
 
 import numpy as np
@@ -10,6 +12,7 @@ from oracle import fno as of
 
 pytestmark = pytest.mark.gpu
 BOUND = 3e-2
+GRAD_BOUND = 1e-2
 
 
 def _say(*a):
@@ -71,7 +74,7 @@ def test_fno_forward_and_gradients_match_oracle(n, w, m, L, h):
         worst[k] = r
     print("grad rel", {k: "%.2e" % v for k, v in worst.items()}, flush=True)
     for k, r in worst.items():
-        assert r < BOUND, (k, r)
+        assert r < GRAD_BOUND, (k, r)
 
 
 def test_fno_forward_at_128_matches_oracle():

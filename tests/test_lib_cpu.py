@@ -65,6 +65,13 @@ def test_argument_checks_precede_any_device_work():
     assert init(method=_lib.PF_ARK2, adaptive=1, atol=0.0) == -1
     assert init(mean_strain_mode=2) == -1
     assert init(norm_space=2) == -1 and init(norm_space=-1) == -1
+    # inhomogeneous elasticity: FP64, prescribed mean strain, stable cubic constants
+    inh = dict(elastic_inhom=1, C11p=375.0, C12p=225.0, C44p=180.0)
+    assert init(precision=_lib.PF_MIXED, **inh) == -1
+    assert init(mean_strain_mode=1, **inh) == -1
+    assert init(**dict(inh, C12p=400.0)) == -1 and init(**dict(inh, C44p=0.0)) == -1
+    assert init(el_max_iter=-1, **inh) == -1 and init(el_tol=-1.0, **inh) == -1
+    assert init(elastic_inhom=2) == -1
     assert init(nx=7) == -4 and init(nz=88) == -4
     # ensembles: cubic supported sizes, one embedded method, one precision
     arr = (_lib.Params * 2)()
@@ -79,6 +86,9 @@ def test_argument_checks_precede_any_device_work():
     assert L.pf_ensemble_init(2, arr, None, ctypes.byref(h)) == -1          # mixed methods
     arr[1] = _lib.make_params(48, None, norm_space=1)
     assert L.pf_ensemble_init(2, arr, None, ctypes.byref(h)) == -1          # k-space norm only
+    arr[1] = _lib.make_params(48, dict(C11p=375.0, C12p=225.0, C44p=180.0))
+    assert arr[1].elastic_inhom == 1
+    assert L.pf_ensemble_init(2, arr, None, ctypes.byref(h)) == -1          # homogeneous elasticity only
     arr[1] = _lib.make_params(48, None, precision="mixed")
     assert L.pf_ensemble_init(2, arr, None, ctypes.byref(h)) == -1
     # the surrogate's shape limits
