@@ -445,6 +445,19 @@ pf_status pf_fno_advance(pf_fno* f, pf_ctx* plain, double* state, int32_t n_adv,
  * and pinned host) per call.  Errors: PF_ERR_ARG (NULL pointer, n < 1),
  * PF_ERR_OOM, PF_ERR_HIP. */
 pf_status pf_rel_l2(const double* a, const double* b, int64_t n, void* hip_stream, double* out);
+/* For callers that cannot allocate (code under stream capture, tight serving
+ * loops, harnesses that forbid hipMalloc): pf_rel_l2 without any allocation.
+ * Same arguments, kernel and summation order as pf_rel_l2 (bit-identical
+ * result).  Its partial sums (512 pairs, 8 KiB) live in a file-scope device
+ * array of the library, one per GPU, held until the process ends; the host
+ * copy of the partials is a stack array.  The array's address is looked up
+ * once per device on the first call there.  Every call on a GPU shares that
+ * GPU's array: calls that overlap on one GPU (other threads or streams) race
+ * and must be serialised by the caller.  Accepts 1 <= n <= 2^41 (each
+ * thread's partial sum then adds at most 2^24 squares); PF_ERR_ARG beyond
+ * that or for NULL pointers, PF_ERR_HIP for a failed HIP call (more than 64
+ * devices included).  Synchronises hip_stream. */
+pf_status pf_rel_l2_noalloc(const double* a, const double* b, int64_t n, void* hip_stream, double* out);
 
 /* Streaming-bandwidth probe (a measurement aid, not part of the method): on
  * hip_stream (NULL = default) times a device copy of `bytes`, a read-only sum

@@ -167,6 +167,8 @@ _SIGS = {
                                           ctypes.POINTER(ctypes.c_double)]),
     "pf_rel_l2": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
                                  ctypes.POINTER(ctypes.c_double)]),
+    "pf_rel_l2_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                         ctypes.POINTER(ctypes.c_double)]),
     "pf_profile_enable": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "pf_profile_classes": (ctypes.c_int32, []),
     "pf_profile_name": (ctypes.c_char_p, [ctypes.c_int32]),

@@ -23,6 +23,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -970,6 +971,11 @@ pf_status pf_fno_adam_step(pf_fno* F, float lr, float beta1, float beta2, float 
 }
 
 static constexpr int kL2Blocks = 512;
+// pf_rel_l2_noalloc: devices it keeps a scratch address for, and the largest
+// count it takes (the per-thread partial sums of 512 x 256 threads then add at
+// most 2^24 squares each)
+static constexpr int kMaxDevices = 64;
+static constexpr int64_t kNoallocMaxN = (int64_t)1 << 41;
 
 // ||a - b|| / ||b|| with caller-provided partials (device) and staging (pinned host)
 static pf_status rel_l2_impl(hipStream_t s, const double* a, const double* b, long long n, double* part,
@@ -977,6 +983,52 @@ static pf_status rel_l2_impl(hipStream_t s, const double* a, const double* b, lo
   k_rel_l2<<<kL2Blocks, 256, 0, s>>>(a, b, n, part);
   FH(hipGetLastError());
   FH(hipMemcpyAsync(host, part, sizeof(double) * 2 * kL2Blocks, hipMemcpyDeviceToHost, s));
+  FH(hipStreamSynchronize(s));
+  double d2 = 0.0, b2 = 0.0;
+  for (int i = 0; i < kL2Blocks; ++i) {
+    d2 += host[2 * i];
+    b2 += host[2 * i + 1];
+  }
+  *out = b2 > 0.0 ? std::sqrt(d2 / b2) : std::sqrt(d2);
+  return PF_OK;
+}
+
+// ---- allocation-free relative L2 ------------------------------------------------
+// The partial sums of pf_rel_l2_noalloc live in a file-scope device array (one
+// copy per GPU, held until the process ends).  In host code `scratch` names a
+// host-side stand-in, not device memory: the array is only ever reached
+// through the address hipGetSymbolAddress returns for the current device,
+// looked up once per device on the entry point's first call there.
+static __device__ __align__(256) double scratch[2 * kL2Blocks];
+static std::mutex g_scratch_mu;
+static double* g_scratch_ptr[kMaxDevices] = {nullptr};
+
+static pf_status scratch_for_current_device(double** out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return PF_ERR_HIP;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return PF_ERR_HIP;
+    g_scratch_ptr[dev] = (double*)p;
+  }
+  *out = g_scratch_ptr[dev];
+  return PF_OK;
+}
+
+pf_status pf_rel_l2_noalloc(const double* a, const double* b, int64_t n, void* stream, double* out) {
+  if (!a || !b || n < 1 || !out) return PF_ERR_ARG;
+  if (n > kNoallocMaxN) return PF_ERR_ARG;
+  double* part = nullptr;
+  pf_status st = scratch_for_current_device(&part);
+  if (st != PF_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  // the same kernel and host-side summation order as pf_rel_l2; the host copy of
+  // the partials is a stack array (no pinned or device allocation)
+  double host[2 * kL2Blocks];
+  k_rel_l2<<<kL2Blocks, 256, 0, s>>>(a, b, n, part);
+  FH(hipGetLastError());
+  FH(hipMemcpyAsync(host, part, sizeof(host), hipMemcpyDeviceToHost, s));
   FH(hipStreamSynchronize(s));
   double d2 = 0.0, b2 = 0.0;
   for (int i = 0; i < kL2Blocks; ++i) {
