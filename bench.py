@@ -440,8 +440,11 @@ def oracle_timing(sizes_rhs=(64, 128, 256), sizes_step=(64, 128), threads=None):
         for n in sizes_rhs:
             spec, c, eta = pfinputs.config("mixed512", n=n)
             m = om.Model((n, n, n), pfinputs.default_params())
+            t0 = time.perf_counter()
             m.B()
+            out["rhs"]["setup_%s_%d" % (backend, n)] = round(time.perf_counter() - t0, 3)
             y = om.to_kspace(c, eta)
+            del c, eta
             t0 = time.perf_counter()
             m.rhs(y)
             wall = time.perf_counter() - t0
@@ -550,29 +553,38 @@ def fno_bench(torch, t_final, runs, val_runs, snapshots, epochs, train_s, member
                        vf_err_max_surrogate=max(r["vf_err_surrogate"] for r in res),
                        fallbacks=sum(r["fallbacks"] for r in res), per_member=res)
     if ensemble:
-        # the whole uneven ensemble: batched plain solver for every member, against batched
-        # plain for the other sizes plus the checked surrogate for the 128^3 members
+        # the whole uneven ensemble: every member on the batched plain solver, against the
+        # same ensemble with its 128^3 members advanced by the surrogate inside it (one
+        # batched network pass for all of them per interval; their checks and fallback
+        # intervals through the ensemble's plain solver) and the other sizes by the plain
+        # solver afterwards
         from paper_2609_36100_amd import Ensemble
         allm = pfinputs.ensemble_members(64)
-        rest = [m for m in allm if m["n"] != n]
+        idx128 = [i for i, m in enumerate(allm) if m["n"] == n]
         walls = {}
-        for name, group in (("all_plain", allm), ("other_sizes_plain", rest)):
-            log("ensemble %s (%d members) to t=%g" % (name, len(group), t_end))
-            with Ensemble([dict(n=m["n"], **kw) for m in group]) as E:
-                for i, m in enumerate(group):
+        vf_end = {}
+        for name in ("all_plain", "with_surrogate"):
+            log("ensemble %s (%d members, %d of %d^3) to t=%g" % (name, len(allm), len(idx128), n, t_end))
+            with Ensemble([dict(n=m["n"], **kw) for m in allm]) as E:
+                for i, m in enumerate(allm):
                     E.set_state(i, m["c"], m["eta"])
                 torch.cuda.synchronize()
                 ta = time.perf_counter()
+                if name == "with_surrogate":
+                    est = f.ensemble_advance(E, idx128, n_adv, delta, check_every=5, tol=1e-3)
                 E.advance(t_end)
                 torch.cuda.synchronize()
                 walls[name] = time.perf_counter() - ta
-        full128 = sum(1 for m in allm if m["n"] == n)
-        sur_all = tot_sur * full128 / max(len(mem), 1)
+                vf_end[name] = [E.diagnostics(i)["vf"] for i in idx128]
+        d = [x.as_dict() for x in est]
         out["gain"]["ensemble"] = dict(
-            members=len(allm), members_128=full128, all_plain_s=round(walls["all_plain"], 3),
-            other_sizes_plain_s=round(walls["other_sizes_plain"], 3),
-            with_surrogate_s=round(walls["other_sizes_plain"] + sur_all, 3),
-            speedup=round(walls["all_plain"] / (walls["other_sizes_plain"] + sur_all), 3))
+            members=len(allm), members_128=len(idx128), all_plain_s=round(walls["all_plain"], 3),
+            with_surrogate_s=round(walls["with_surrogate"], 3),
+            speedup=round(walls["all_plain"] / walls["with_surrogate"], 3),
+            surrogate_advances=sum(x["surrogate"] for x in d), checks=sum(x["checks"] for x in d),
+            fallbacks=sum(x["fallbacks"] for x in d), plain_advances=sum(x["plain"] for x in d),
+            vf_diff_max=float("%.3e" % max(abs(a - b) for a, b in zip(vf_end["all_plain"],
+                                                                        vf_end["with_surrogate"]))))
     return out
 
 
@@ -653,6 +665,8 @@ def main():
     ap.add_argument("--members", type=int, default=64)
     ap.add_argument("--batched-only", action="store_true",
                     help="ensemble: the batched runs alone (no sequential or reference runs)")
+    ap.add_argument("--rhs-sizes", default="64,128,256",
+                    help="oracle_timing: grid sizes for the one-RHS timing (512 needs about 40 GB of host memory)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 4 GiB (counter calibration)")
     args = ap.parse_args()
@@ -700,7 +714,7 @@ def main():
                           "fno": r}), flush=True)
         return
     if args.mode == "oracle_timing":
-        r = oracle_timing()
+        r = oracle_timing(sizes_rhs=tuple(int(v) for v in args.rhs_sizes.split(",")))
         print(json.dumps({"metric": METRIC, "mode": "oracle_timing", "unit": "Mpts·stages/s", "value": None,
                           "higher_is_better": True, "n_gpus": 0, "dtype": "f64", "data": "synthetic",
                           "config": {"workload": "FP64 CPU oracle: one RHS and one ARK4 step at several sizes"},

@@ -411,6 +411,14 @@ pf_status pf_fno_train_step(pf_fno* f, const float* x, const float* y, int32_t b
  * restored (the composition is conserved); state / next device float64
  * [cin][n^3] (cin == cout); next may equal state */
 pf_status pf_fno_apply(pf_fno* f, const double* state, double* next);
+/* pf_fno_apply for `batch` samples at once (states / nexts device float64
+ * [batch][cin][n^3]; nexts may equal states): one network pass whose GEMMs
+ * run over every sample's points and lines together, so each sample's result
+ * is bit-identical to pf_fno_apply's.  The batched activations (about
+ * 1.2 GB per 128^3 sample at width 32, hidden 128) are allocated on the
+ * first call and grown when a larger batch comes.  Errors: PF_ERR_ARG (batch
+ * < 1, NULL, cin != cout), PF_ERR_OOM, PF_ERR_HIP. */
+pf_status pf_fno_apply_batch(pf_fno* f, const double* states, double* nexts, int32_t batch);
 
 /* Counters of the checked surrogate advance.  since_check and plain_left are
  * carried between calls: zero the struct before a member's first call and
@@ -439,6 +447,24 @@ typedef struct {
  * overwritten; its stream must be ordered with the network's).  Synchronous. */
 pf_status pf_fno_advance(pf_fno* f, pf_ctx* plain, double* state, int32_t n_adv, double delta,
                          int32_t check_every, double tol, pf_fno_stats* stats);
+/* The checked advance inside a batched ensemble: the `count` members listed
+ * (0-based, distinct, each on the network's n^3 grid) advance by n_adv
+ * intervals of length delta with the rules of pf_fno_advance (every
+ * check_every-th surrogate advance of a member recomputed by the plain
+ * solver from the same input; above tol the plain result replaces it and the
+ * member runs check_every intervals on the plain solver).  Per interval, every
+ * listed member goes through ONE batched network pass (pf_fno_apply_batch)
+ * and every check and plain interval runs in ONE pf_ensemble_advance of the
+ * ensemble's own batched solver (with the ensemble's method, tolerances and
+ * step control; members not listed stay where they are).  Each member ends
+ * at its starting time plus n_adv delta, keeping its proposed step size.
+ * stats[count]: as pf_fno_advance's, carried between calls; ms_surrogate and
+ * ms_plain are the whole call's network and plain wall times, the same in
+ * every member's entry.  Synchronous.  Errors: PF_ERR_ARG (bad index,
+ * duplicate, size mismatch, cin or cout != 4, delta <= 0, check_every < 1,
+ * tol < 0), PF_ERR_OOM, PF_ERR_HIP, and the ensemble's own errors. */
+pf_status pf_fno_ensemble_advance(pf_fno* f, pf_ens* ens, const int32_t* members, int32_t count, int32_t n_adv,
+                                  double delta, int32_t check_every, double tol, pf_fno_stats* stats);
 /* ||a - b||_2 / ||b||_2 over n device float64 values (||a - b|| if b == 0),
  * the error measure of the surrogate's checks; ordered on hip_stream (NULL =
  * default); synchronises that stream.  Allocates its partial sums (device

@@ -451,6 +451,25 @@ class FNO:
         """out = state + scale * net(state), mean of c restored (device float64 (cin, n, n, n))."""
         _lib.check(_lib.lib().pf_fno_apply(self._h, _ptr(state), _ptr(out)), "pf_fno_apply")
 
+    def apply_batch(self, states, out):
+        """out[b] = states[b] + scale * net(states[b]) for every b (device float64 (B, cin, n, n, n))."""
+        assert states.is_contiguous() and out.is_contiguous() and states.shape == out.shape
+        _lib.check(_lib.lib().pf_fno_apply_batch(self._h, _ptr(states), _ptr(out), int(states.shape[0])),
+                   "pf_fno_apply_batch")
+
+    def ensemble_advance(self, ens, members, n_adv, delta, check_every=5, tol=1e-3, stats=None):
+        """Checked surrogate advance of the listed members of an :class:`Ensemble` (see
+        pf_fno_ensemble_advance); ``stats`` (a list of FnoStats, one per member) carries the
+        cadence between calls; returns it."""
+        idx = (ctypes.c_int32 * len(members))(*[int(m) for m in members])
+        if stats is None:
+            stats = [_lib.FnoStats() for _ in members]
+        arr = (_lib.FnoStats * len(members))(*stats)
+        _lib.check(_lib.lib().pf_fno_ensemble_advance(self._h, ens._h, idx, len(members), int(n_adv), float(delta),
+                                                      int(check_every), float(tol), arr),
+                   "pf_fno_ensemble_advance")
+        return [arr[i] for i in range(len(members))]
+
     def advance(self, plain, state, n_adv, delta, check_every=5, tol=1e-3, stats=None):
         """Checked surrogate advance of ``state`` (device float64 (4, n, n, n), in place) by
         ``n_adv`` intervals of ``delta``; ``plain`` is a :class:`Solver` on the same grid that

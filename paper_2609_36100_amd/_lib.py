@@ -159,6 +159,10 @@ _SIGS = {
                                         ctypes.c_float, ctypes.c_float]),
     "pf_fno_set_input_norm": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "pf_fno_apply": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "pf_fno_apply_batch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32]),
+    "pf_fno_ensemble_advance": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32),
+                                               ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_int32,
+                                               ctypes.c_double, ctypes.POINTER(FnoStats)]),
     "pf_fno_advance": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
                                       ctypes.c_double, ctypes.c_int32, ctypes.c_double,
                                       ctypes.POINTER(FnoStats)]),

@@ -249,4 +249,10 @@ void make_twiddles32(int n, cx<float>* host);
 // mass, volume fraction, threshold fraction and (want_F) total free energy of
 // the context's current state; F is NaN without want_F
 pf_status ctx_diagnostics(pf_ctx* c, bool want_F, double out[4]);
+// ensemble member access (defined in pf_ensemble.hip)
+int ens_members(const pf_ens* E);
+int ens_member_n(const pf_ens* E, int m);
+double ens_member_time(const pf_ens* E, int m);
+hipStream_t ens_stream(const pf_ens* E);
+pf_status ens_member_set(pf_ens* E, int m, const double* u, double t);
 }  // namespace pf

@@ -92,9 +92,16 @@ enum EKind { EK_STAGE = 0, EK_YFFT4, EK_YFFT3, EK_THETA, EK_ELASTIC, EK_DRIVE, E
 static const char* const ek_names[EK_COUNT] = {"stage_invz", "ypass4", "ypass3", "xpass_theta",
                                                "zpass_elastic", "xpass_drive", "zpass_fwd_ac"};
 
+// Columns per work-group of eb threads for lines of n points: the largest
+// power of two that fits, so every row segment starts on a 128-byte boundary
+// (a width like 10 or 21 columns for the 48- and 96-point lines would make
+// each segment straddle cache lines); the remaining threads idle.
 constexpr int ens_tx(int eb, int n, int re) {
   const int tl = line_threads(n, re);
-  return eb / tl < 1 ? 1 : eb / tl;
+  const int fit = eb / tl < 1 ? 1 : eb / tl;
+  int tx = 1;
+  while (2 * tx <= fit) tx *= 2;
+  return tx;
 }
 constexpr int ens_rb(int eb, int m) {
   const int tl = line_threads(m);
@@ -864,6 +871,35 @@ pf_status pf_ensemble_free_energy(pf_ens* E, int32_t m, double* F) {
   if (s != PF_OK) return s;
   return pf_free_energy(v, F);
 }
+
+}  // extern "C"
+
+namespace pf {
+// Member access for the surrogate's ensemble advance (same library).
+int ens_members(const pf_ens* E) { return E ? E->M : 0; }
+int ens_member_n(const pf_ens* E, int m) { return (E && m >= 0 && m < E->M) ? E->prm[m].nz : 0; }
+double ens_member_time(const pf_ens* E, int m) { return (E && m >= 0 && m < E->M) ? E->st_host[m].t : 0.0; }
+hipStream_t ens_stream(const pf_ens* E) { return E ? E->stream : nullptr; }
+// Sets member m's real-space state (device [4][n^3]) and time t, keeping its
+// proposed step size and its step counters.
+pf_status ens_member_set(pf_ens* E, int m, const double* u, double t) {
+  if (!E || m < 0 || m >= E->M || !u) return PF_ERR_ARG;
+  EState& x = E->st_host[m];
+  x.cur = 0;
+  pf_ctx* v;
+  pf_status s = view_for(E, m, &v);
+  if (s != PF_OK) return s;
+  const long long P = (long long)v->g.nx * v->g.ny * v->g.nz;
+  s = pf_set_state(v, u, u + P, 1, t);
+  if (s != PF_OK) return s;
+  x.t = t;
+  x.rejrow = 0;
+  x.done = 1;
+  return PF_OK;
+}
+}  // namespace pf
+
+extern "C" {
 
 int64_t pf_ensemble_kspace_pitch(const pf_ens* E, int32_t m) {
   if (!E || m < 0 || m >= E->M) return 0;

@@ -9,7 +9,7 @@
 // retained modes kx < m and ky, kz in the m lowest positive and negative
 // frequencies.  Activations are channel-last [point][channel] BF16.
 //
-// Dense contractions run on MFMA (v_mfma_f32_32x32x8bf16_1k, FP32 accumulate):
+// Dense contractions run on MFMA (gfx950 v_mfma_f32_32x32x16_bf16, FP32 accumulate):
 //  * channel mixing (lift, W_l, P1, P2 and their data gradients) as
 //    [points x K] x [K x N] GEMMs;
 //  * every truncated-DFT stage as a small constant matrix G times batched
@@ -28,12 +28,26 @@
 #include <vector>
 
 #include "../../include/pf.h"
+#include "pf_context.hpp"
 
 namespace {
 
 typedef unsigned short u16;
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef short s16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+// gfx950's 32 x 32 x 16 BF16 MFMA (FP32 accumulate).  Lane l holds row l % 32
+// of A and column l % 32 of B at k = 8 (l / 32) .. 8 (l / 32) + 7; the
+// accumulator layout is that of every 32 x 32 MFMA (lane l, element i: row
+// 8 (i / 4) + 4 (l / 32) + i % 4, column l % 32).
+__device__ inline f32x16 mfma16(bf16x4 a_lo, bf16x4 a_hi, bf16x4 b_lo, bf16x4 b_hi, f32x16 acc) {
+  const s16x8 a = {a_lo[0], a_lo[1], a_lo[2], a_lo[3], a_hi[0], a_hi[1], a_hi[2], a_hi[3]};
+  const s16x8 b = {b_lo[0], b_lo[1], b_lo[2], b_lo[3], b_hi[0], b_hi[1], b_hi[2], b_hi[3]};
+  return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), acc,
+                                                 0, 0, 0);
+}
 
 __host__ __device__ inline u16 f2bf(float f) {
   unsigned int u;
@@ -71,16 +85,20 @@ k_cm_gemm(const u16* __restrict__ In, int ldin, int K, const u16* __restrict__ B
   for (int t = 0; t < NT; ++t)
 #pragma unroll
     for (int i = 0; i < 16; ++i) acc[t][i] = 0.0f;
-  for (int kk = 0; kk < K; kk += 8) {
-    const bool kin = kk + lg * 4 < K;  // K % 4 == 0: a 4-wide group is all in or all out
-    bf16x4 a = {0, 0, 0, 0};
-    if (kin) a = ld4(In + (p0 + lr) * ldin + kk + lg * 4);
+  for (int kk = 0; kk < K; kk += 16) {
+    // K % 4 == 0: each 4-wide half of a lane's 8 values is all in or all out
+    const int kb = kk + lg * 8;
+    const bool in0 = kb < K, in1 = kb + 4 < K;
+    bf16x4 a0 = {0, 0, 0, 0}, a1 = {0, 0, 0, 0};
+    if (in0) a0 = ld4(In + (p0 + lr) * ldin + kb);
+    if (in1) a1 = ld4(In + (p0 + lr) * ldin + kb + 4);
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
       const int n = t * 32 + lr;
-      bf16x4 b = {0, 0, 0, 0};
-      if (n < N && kin) b = ld4(Bt + (long long)n * K + kk + lg * 4);
-      acc[t] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc[t], 0, 0, 0);
+      bf16x4 b0 = {0, 0, 0, 0}, b1 = {0, 0, 0, 0};
+      if (n < N && in0) b0 = ld4(Bt + (long long)n * K + kb);
+      if (n < N && in1) b1 = ld4(Bt + (long long)n * K + kb + 4);
+      acc[t] = mfma16(a0, a1, b0, b1, acc[t]);
     }
   }
 #pragma unroll
@@ -124,21 +142,26 @@ k_lm_gemm(const u16* __restrict__ G, int R, int K, const u16* __restrict__ X, lo
     for (int t = 0; t < 4; ++t)
 #pragma unroll
       for (int i = 0; i < 16; ++i) acc[t][i] = 0.0f;
-    for (int kk = 0; kk < K; kk += 8) {
-      const int kb = kk + lg * 4;
-      const bool kin = kb < K;  // K % 4 == 0
-      bf16x4 bv = {0, 0, 0, 0};
-      if (valid && kin) {
+    for (int kk = 0; kk < K; kk += 16) {
+      const int kb = kk + lg * 8;
+      const bool in0 = kb < K, in1 = kb + 4 < K;  // K % 4 == 0
+      bf16x4 b0 = {0, 0, 0, 0}, b1 = {0, 0, 0, 0};
+      if (valid && in0) {
 #pragma unroll
-        for (int j = 0; j < 4; ++j) bv[j] = (short)Xb[(long long)(kb + j) * ldx + n];
+        for (int j = 0; j < 4; ++j) b0[j] = (short)Xb[(long long)(kb + j) * ldx + n];
+      }
+      if (valid && in1) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) b1[j] = (short)Xb[(long long)(kb + 4 + j) * ldx + n];
       }
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
         const int r = r0 + t * 32 + lr;
         if (r0 + t * 32 < R) {
-          bf16x4 av = {0, 0, 0, 0};
-          if (r < R && kin) av = ld4(G + (long long)r * K + kb);
-          acc[t] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(av, bv, acc[t], 0, 0, 0);
+          bf16x4 a0 = {0, 0, 0, 0}, a1 = {0, 0, 0, 0};
+          if (r < R && in0) a0 = ld4(G + (long long)r * K + kb);
+          if (r < R && in1) a1 = ld4(G + (long long)r * K + kb + 4);
+          acc[t] = mfma16(a0, a1, b0, b1, acc[t]);
         }
       }
     }
@@ -160,14 +183,20 @@ k_lm_gemm(const u16* __restrict__ G, int R, int K, const u16* __restrict__ X, lo
 
 // ---- per-mode complex mixing (FP32) -------------------------------------------
 // S, T: [2][modes][w] (real block, imaginary block); R: [modes][w][w] (in, out).
+// `batches` spectra one after another (stride 2 modes w), the same weights.
 __global__ void __launch_bounds__(256)
 k_mix_fwd(const float* __restrict__ S, const u16* __restrict__ Rr, const u16* __restrict__ Ri, float* __restrict__ T,
-          int modes, int w, u16* __restrict__ Tb) {
-  const long long id = blockIdx.x * 256LL + threadIdx.x;
-  if (id >= (long long)modes * w) return;
+          int modes, int w, u16* __restrict__ Tb, int batches) {
+  const long long gid = blockIdx.x * 256LL + threadIdx.x;
+  const long long mo = (long long)modes * w;
+  if (gid >= mo * batches) return;
+  const long long bo = (gid / mo) * 2 * mo;  // this spectrum's offset
+  S += bo;
+  T += bo;
+  Tb += bo;
+  const long long id = gid % mo;
   const long long md = id / w;
   const int o = (int)(id % w);
-  const long long mo = (long long)modes * w;
   float tr = 0.f, ti = 0.f;
   for (int i = 0; i < w; ++i) {
     const float sr = S[md * w + i], si = S[mo + md * w + i];
@@ -218,7 +247,7 @@ k_mix_bwd_w(const float* __restrict__ S, const float* __restrict__ dT, float* __
 // The reduction runs over points, which are the slow index of both operands,
 // so each block stages WG_PTS points of A (bf16) and D (f32, rounded to bf16)
 // transposed into LDS ([channel][point], padded rows) and every wave feeds
-// 32 of those points to v_mfma_f32_32x32x8bf16_1k for up to four 32 x 32
+// 32 of those points to the 32 x 32 x 16 MFMA for up to four 32 x 32
 // output tiles [t0, t0 + 4) of the ceil(K/32) x ceil(N/32) tile grid.  The
 // four waves' tiles are summed in LDS and each block writes one partial set
 // part[block * KN + k * N + n] (KN = (K + 1) * N; row k = K holds the bias
@@ -274,13 +303,16 @@ k_wgrad_mfma(const u16* __restrict__ A, int lda, int K, const float* __restrict_
     for (int t = 0; t < 4; ++t) {
       if (t >= ntiles) break;
       const int tile = t0 + t, kt = tile / Nt, nt = tile % Nt;
-      const u16* ra = LA + (kt * 32 + lr) * WG_LD + wave * 32 + lg * 4;
-      const u16* rb = LD + (nt * 32 + lr) * WG_LD + wave * 32 + lg * 4;
+      const u16* ra = LA + (kt * 32 + lr) * WG_LD + wave * 32 + lg * 8;
+      const u16* rb = LD + (nt * 32 + lr) * WG_LD + wave * 32 + lg * 8;
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const bf16x4 a = *reinterpret_cast<const bf16x4*>(ra + 8 * j);
-        const bf16x4 b = *reinterpret_cast<const bf16x4*>(rb + 8 * j);
-        acc[t] = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc[t], 0, 0, 0);
+      for (int j = 0; j < 2; ++j) {
+        // 8-byte LDS reads (rows are 8-byte aligned)
+        const bf16x4 a0 = *reinterpret_cast<const bf16x4*>(ra + 16 * j);
+        const bf16x4 a1 = *reinterpret_cast<const bf16x4*>(ra + 16 * j + 4);
+        const bf16x4 b0 = *reinterpret_cast<const bf16x4*>(rb + 16 * j);
+        const bf16x4 b1 = *reinterpret_cast<const bf16x4*>(rb + 16 * j + 4);
+        acc[t] = mfma16(a0, a1, b0, b1, acc[t]);
       }
     }
   }
@@ -516,6 +548,17 @@ struct pf_fno {
   double* dpart = nullptr;
   double* dsum = nullptr;
   double* hsum = nullptr;  // pinned
+  // batched inference over `bcap` samples (allocated on first use, grown on demand)
+  int bcap = 0;
+  std::vector<void*> ballocs;
+  u16 *bxin = nullptr, *bv0 = nullptr, *bv1 = nullptr, *bA1 = nullptr, *bA2 = nullptr, *bTb = nullptr, *bB3 = nullptr,
+      *bB2 = nullptr, *bhact = nullptr;
+  float *bS = nullptr, *bT = nullptr, *bB1 = nullptr, *boutf = nullptr;
+  double *bdpart = nullptr, *bdsum = nullptr;
+  // ensemble surrogate advance: current, network and plain states of `ecap` members
+  int ecap = 0;
+  std::vector<void*> eallocs;
+  double *eX = nullptr, *eY = nullptr, *eP = nullptr;
   // checked-advance buffers (allocated on first use)
   double* adv_next = nullptr;
   double* adv_ref = nullptr;
@@ -666,7 +709,7 @@ static void forward(pf_fno* F) {
     lm(F, F->Gzf, 2 * m2, 2 * n, F->A2, 0, Nz, Nz, 1, F->S[l], nullptr, 0, Nz, 0);
     // per-mode mixing
     k_mix_fwd<<<gdiv((long long)F->mode_count * w, 256), 256, 0, F->stream>>>(F->S[l], F->bRr[l], F->bRi[l], F->T,
-                                                                               F->mode_count, w, F->Tb);
+                                                                               F->mode_count, w, F->Tb, 1);
     // inverse: z, y (batch z), x (batch z,y)
     lm(F, F->Gzi, 2 * n, 2 * m2, F->Tb, 0, Nz, Nz, 1, nullptr, F->B3, 0, Nz, 0);
     lm(F, F->Gyi, 2 * n, 2 * m2, F->B3, (long long)2 * m2 * m * w, m * w, m * w, n, nullptr, F->B2,
@@ -847,6 +890,8 @@ void pf_fno_destroy(pf_fno* F) {
   if (!F) return;
   if (F->stream) hipStreamSynchronize(F->stream);
   for (void* p : F->allocs) hipFree(p);
+  for (void* p : F->ballocs) hipFree(p);
+  for (void* p : F->eallocs) hipFree(p);
   if (F->hsum) hipHostFree(F->hsum);
   if (F->l2_host) hipHostFree(F->l2_host);
   delete F;
@@ -1055,6 +1100,133 @@ pf_status pf_rel_l2(const double* a, const double* b, int64_t n, void* stream, d
   return st;
 }
 
+}  // extern "C"
+
+// ---- batched inference ---------------------------------------------------------
+static pf_status grow(std::vector<void*>& list, void** p, size_t bytes) {
+  if (hipMalloc(p, bytes) != hipSuccess) {
+    *p = nullptr;
+    return PF_ERR_OOM;
+  }
+  list.push_back(*p);
+  return PF_OK;
+}
+
+// Inference buffers for B samples (the forward pass's activations, B times;
+// no pre-activations or gradients are kept).
+static pf_status ensure_batch(pf_fno* F, int B) {
+  if (B <= F->bcap) return PF_OK;
+  hipStreamSynchronize(F->stream);
+  for (void* p : F->ballocs) hipFree(p);
+  F->ballocs.clear();
+  F->bcap = 0;
+  const pf_fno_config& c = F->cfg;
+  const size_t w = c.width, m = c.modes, m2 = 2 * m, h = c.hidden, n = c.n, P = (size_t)F->P, Bs = (size_t)B;
+  const size_t Nz = m2 * m * w, spec = 2 * (size_t)F->mode_count * w;
+  const size_t a1 = std::max(n * n * 2 * m * w, n * 2 * n * m * w);
+  pf_status s = PF_OK;
+  auto A = [&](void** p, size_t bytes) {
+    if (s == PF_OK) s = grow(F->ballocs, p, bytes);
+  };
+  A((void**)&F->bxin, Bs * 2 * P * F->cinp);
+  A((void**)&F->bv0, Bs * 2 * P * w);
+  A((void**)&F->bv1, Bs * 2 * P * w);
+  A((void**)&F->bA1, Bs * 2 * a1);
+  A((void**)&F->bA2, Bs * 2 * 2 * n * Nz);
+  A((void**)&F->bS, Bs * 4 * spec);
+  A((void**)&F->bT, Bs * 4 * spec);
+  A((void**)&F->bTb, Bs * 2 * spec);
+  A((void**)&F->bB3, Bs * 2 * 2 * n * Nz);
+  A((void**)&F->bB2, Bs * 2 * a1);
+  A((void**)&F->bB1, Bs * 4 * P * w);
+  A((void**)&F->bhact, Bs * 2 * P * h);
+  A((void**)&F->boutf, Bs * 4 * P * c.cout);
+  A((void**)&F->bdpart, Bs * 8 * gdiv(F->P, 256));
+  A((void**)&F->bdsum, Bs * 8);
+  if (s != PF_OK) {
+    for (void* p : F->ballocs) hipFree(p);
+    F->ballocs.clear();
+    return s;
+  }
+  F->bcap = B;
+  return PF_OK;
+}
+
+static void cm_points(pf_fno* F, long long points, const u16* In, int ldin, int K, const u16* Bt, int N,
+                      const float* bias, const float* resid, int ldres, float* outf, u16* outpre, u16* outact,
+                      int ldout) {
+  const unsigned grid = (unsigned)(points / 128);
+  if (N <= 32)
+    k_cm_gemm<1><<<grid, 256, 0, F->stream>>>(In, ldin, K, Bt, N, bias, resid, ldres, outf, outpre, outact, ldout, 0);
+  else
+    k_cm_gemm<4><<<grid, 256, 0, F->stream>>>(In, ldin, K, Bt, N, bias, resid, ldres, outf, outpre, outact, ldout, 0);
+}
+
+// The forward pass of B samples at once (inputs packed in bxin, outputs in
+// boutf): every channel-mixing GEMM runs over the B n^3 points together and
+// every truncated-DFT stage takes the B samples' lines as more batches of the
+// same small GEMM, so the sums are those of the one-sample pass.
+static void forward_batch(pf_fno* F, int B) {
+  const pf_fno_config& c = F->cfg;
+  const int n = c.n, w = c.width, m = c.modes, m2 = 2 * m, h = c.hidden;
+  const long long PB = F->P * B;
+  const long long Nz = (long long)m2 * m * w, spec = 2LL * F->mode_count * w;
+  const float* th = F->th;
+  cm_points(F, PB, F->bxin, F->cinp, F->cinp, F->bWliftT, w, th + F->o_bl, nullptr, 0, nullptr, F->bv0, nullptr, w);
+  u16* v = F->bv0;
+  u16* vn = F->bv1;
+  for (int l = 0; l < c.layers; ++l) {
+    lm(F, F->Gxf, 2 * m, n, v, (long long)n * w, w, w, B * n * n, nullptr, F->bA1, (long long)2 * m * w, w, 0);
+    lm(F, F->Gyf, 2 * m2, 2 * n, F->bA1, (long long)n * 2 * m * w, m * w, m * w, B * n, nullptr, F->bA2,
+       (long long)2 * m2 * m * w, m * w, 0);
+    lm(F, F->Gzf, 2 * m2, 2 * n, F->bA2, 2LL * n * Nz, (int)Nz, (int)Nz, B, F->bS, nullptr, spec, (int)Nz, 0);
+    k_mix_fwd<<<gdiv((long long)F->mode_count * w * B, 256), 256, 0, F->stream>>>(F->bS, F->bRr[l], F->bRi[l],
+                                                                                   F->bT, F->mode_count, w,
+                                                                                   F->bTb, B);
+    lm(F, F->Gzi, 2 * n, 2 * m2, F->bTb, spec, (int)Nz, (int)Nz, B, nullptr, F->bB3, 2LL * n * Nz, (int)Nz, 0);
+    lm(F, F->Gyi, 2 * n, 2 * m2, F->bB3, (long long)2 * m2 * m * w, m * w, m * w, B * n, nullptr, F->bB2,
+       (long long)2 * n * m * w, m * w, 0);
+    lm(F, F->Gxi, n, 2 * m, F->bB2, (long long)2 * m * w, w, w, B * n * n, F->bB1, nullptr, (long long)n * w, w, 0);
+    const bool last = l == c.layers - 1;
+    cm_points(F, PB, v, w, w, F->bWT[l], w, th + F->o_b[l], F->bB1, w, nullptr, last ? vn : nullptr,
+              last ? nullptr : vn, w);
+    std::swap(v, vn);
+  }
+  cm_points(F, PB, v, w, w, F->bP1T, h, th + F->o_c1, nullptr, 0, nullptr, nullptr, F->bhact, h);
+  cm_points(F, PB, F->bhact, h, h, F->bP2T, c.cout, th + F->o_c2, nullptr, 0, F->boutf, nullptr, nullptr, c.cout);
+}
+
+// next_b = state_b + scale * net(state_b), mean of c restored, for b < B
+// (states / nexts: [B][cin][n^3] float64; next may equal state).
+static pf_status apply_batch(pf_fno* F, const double* states, double* nexts, int B) {
+  pf_status s = ensure_batch(F, B);
+  if (s != PF_OK) return s;
+  const long long P = F->P;
+  const int ci = F->cfg.cin, co = F->cfg.cout;
+  const unsigned nb = gdiv(P, 256);
+  for (int b = 0; b < B; ++b)
+    k_pack_input<double><<<nb, 256, 0, F->stream>>>(states + (long long)b * ci * P, P, ci, F->cinp, F->innorm,
+                                                    F->bxin + (long long)b * P * F->cinp);
+  forward_batch(F, B);
+  for (int b = 0; b < B; ++b) {
+    double* nx = nexts + (long long)b * co * P;
+    k_apply<<<nb, 256, 0, F->stream>>>(states + (long long)b * ci * P, F->boutf + (long long)b * P * co, F->scale, P,
+                                       co, nx, F->bdpart + (long long)b * nb);
+    k_sum_d<<<1, 256, 0, F->stream>>>(F->bdpart + (long long)b * nb, (int)nb, F->bdsum + b);
+    k_shift<<<nb, 256, 0, F->stream>>>(nx, P, F->bdsum + b);
+  }
+  FH(hipGetLastError());
+  FH(hipStreamSynchronize(F->stream));
+  return PF_OK;
+}
+
+extern "C" {
+
+pf_status pf_fno_apply_batch(pf_fno* F, const double* states, double* nexts, int32_t batch) {
+  if (!F || !states || !nexts || batch < 1 || F->cfg.cin != F->cfg.cout) return PF_ERR_ARG;
+  return apply_batch(F, states, nexts, batch);
+}
+
 pf_status pf_fno_apply(pf_fno* F, const double* state, double* next) {
   if (!F || !state || !next || F->cfg.cin != F->cfg.cout) return PF_ERR_ARG;
   k_pack_input<double><<<gdiv(F->P, 256), 256, 0, F->stream>>>(state, F->P, F->cfg.cin, F->cinp, F->innorm, F->xin);
@@ -1132,6 +1304,122 @@ pf_status pf_fno_advance(pf_fno* F, pf_ctx* plain, double* state, int32_t n_adv,
     FH(hipStreamSynchronize(F->stream));
     st->ms_plain += ms_since(t0);
   }
+  return PF_OK;
+}
+
+pf_status pf_fno_ensemble_advance(pf_fno* F, pf_ens* E, const int32_t* members, int32_t count, int32_t n_adv,
+                                  double delta, int32_t check_every, double tol, pf_fno_stats* st) {
+  if (!F || !E || !members || !st || count < 1 || n_adv < 0 || !(delta > 0.0) || check_every < 1 || !(tol >= 0.0) ||
+      F->cfg.cin != 4 || F->cfg.cout != 4)
+    return PF_ERR_ARG;
+  const int M = pf::ens_members(E);
+  for (int i = 0; i < count; ++i) {
+    if (members[i] < 0 || members[i] >= M || pf::ens_member_n(E, members[i]) != F->cfg.n) return PF_ERR_ARG;
+    for (int j = 0; j < i; ++j)
+      if (members[j] == members[i]) return PF_ERR_ARG;
+  }
+  const long long P = F->P;
+  const size_t per = 4 * (size_t)P;
+  if (count > F->ecap) {
+    hipStreamSynchronize(F->stream);
+    for (void* p : F->eallocs) hipFree(p);
+    F->eallocs.clear();
+    F->ecap = 0;
+    pf_status s = grow(F->eallocs, (void**)&F->eX, sizeof(double) * per * count);
+    if (s == PF_OK) s = grow(F->eallocs, (void**)&F->eY, sizeof(double) * per * count);
+    if (s == PF_OK) s = grow(F->eallocs, (void**)&F->eP, sizeof(double) * per * count);
+    if (s != PF_OK) return s;
+    F->ecap = count;
+  }
+  if (!F->l2_part) {
+    pf_status s = falloc(F, (void**)&F->l2_part, sizeof(double) * 2 * kL2Blocks);
+    if (s == PF_OK && hipHostMalloc((void**)&F->l2_host, sizeof(double) * 2 * kL2Blocks, 0) != hipSuccess)
+      s = PF_ERR_OOM;
+    if (s != PF_OK) return s;
+  }
+  using clk = std::chrono::steady_clock;
+  auto ms_since = [](clk::time_point t0) {
+    return std::chrono::duration<double, std::milli>(clk::now() - t0).count();
+  };
+  hipStream_t es = pf::ens_stream(E);
+  std::vector<double> t0(count), tf(M);
+  for (int i = 0; i < count; ++i) {
+    t0[i] = pf::ens_member_time(E, members[i]);
+    pf_status s = pf_ensemble_get_state(E, members[i], F->eX + i * per, F->eX + i * per + P, 1);
+    if (s != PF_OK) return s;
+  }
+  double ms_net = 0.0, ms_plain = 0.0;
+  std::vector<char> due(count), plainm(count);
+  for (int32_t a = 0; a < n_adv; ++a) {
+    bool any_net = false, any_plain = false;
+    for (int i = 0; i < count; ++i) {
+      plainm[i] = st[i].plain_left > 0;
+      due[i] = !plainm[i] && st[i].since_check + 1 >= check_every;
+      any_net = any_net || !plainm[i];
+      any_plain = any_plain || plainm[i] || due[i];
+    }
+    auto t1 = clk::now();
+    if (any_net) {  // every member through the network in one batched pass
+      pf_status s = apply_batch(F, F->eX, F->eY, count);
+      if (s != PF_OK) return s;
+    }
+    ms_net += ms_since(t1);
+    t1 = clk::now();
+    if (any_plain) {  // the checks and the plain intervals: one ensemble advance
+      for (int m = 0; m < M; ++m) tf[m] = pf::ens_member_time(E, m);
+      for (int i = 0; i < count; ++i) {
+        if (!(plainm[i] || due[i])) continue;
+        pf_status s = pf::ens_member_set(E, members[i], F->eX + i * per, 0.0);
+        if (s != PF_OK) return s;
+        tf[members[i]] = delta;
+      }
+      pf_status s = pf_ensemble_advance(E, tf.data(), 1 << 30, nullptr);
+      if (s != PF_OK) return s;
+      for (int i = 0; i < count; ++i) {
+        if (!(plainm[i] || due[i])) continue;
+        s = pf_ensemble_get_state(E, members[i], F->eP + i * per, F->eP + i * per + P, 1);
+        if (s != PF_OK) return s;
+      }
+      FH(hipStreamSynchronize(es));
+    }
+    for (int i = 0; i < count; ++i) {
+      pf_fno_stats& x = st[i];
+      const double* src;
+      if (plainm[i]) {
+        x.plain += 1;
+        x.plain_left -= 1;
+        src = F->eP + i * per;
+      } else {
+        x.surrogate += 1;
+        x.since_check += 1;
+        src = F->eY + i * per;
+        if (due[i]) {
+          x.since_check = 0;
+          x.checks += 1;
+          double err = 0.0;
+          pf_status s = rel_l2_impl(F->stream, F->eY + i * per, F->eP + i * per, P, F->l2_part, F->l2_host, &err);
+          if (s != PF_OK) return s;
+          x.err_last = err;
+          if (!(err <= x.err_max)) x.err_max = err;
+          if (!(err <= tol)) {
+            x.fallbacks += 1;
+            x.plain_left = check_every;
+            src = F->eP + i * per;
+          }
+        }
+      }
+      FH(hipMemcpyAsync(F->eX + i * per, src, sizeof(double) * per, hipMemcpyDeviceToDevice, F->stream));
+    }
+    FH(hipStreamSynchronize(F->stream));
+    ms_plain += ms_since(t1);
+  }
+  for (int i = 0; i < count; ++i) {
+    pf_status s = pf::ens_member_set(E, members[i], F->eX + i * per, t0[i] + n_adv * delta);
+    if (s != PF_OK) return s;
+    st[i].ms_surrogate += ms_net;
+    st[i].ms_plain += ms_plain;
+  }
+  FH(hipStreamSynchronize(es));
   return PF_OK;
 }
 

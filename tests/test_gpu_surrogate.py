@@ -167,3 +167,109 @@ def test_trained_network_beats_untrained_and_no_change():
     print("checked advance: %s; final rel-L2(c) vs plain %.3e" % (st.as_dict(), err))
     assert st.surrogate + st.plain == 10 and st.checks == st.surrogate // 5
     assert err < 2e-2
+
+
+def _ens_members(pf, sizes, seed0=40):
+    """Members smoothed by a few plain steps; fixed-step ARK4 so that intervals
+    compose exactly."""
+    import pfinputs
+    mem = []
+    for i, n in enumerate(sizes):
+        ic = pfinputs.surrogate_run(seed0 + i, n, 3000, NUCLEI)
+        with pf.Solver(n, None, method="ark436l", dt0=DT) as s:
+            s.set_state(ic["c"], ic["eta"])
+            s.advance(0.5)
+            c, eta = s.get_state()
+        mem.append((n, c, eta))
+    return mem
+
+
+def test_batched_apply_equals_single_applies():
+    """One network pass over several members gives, bit for bit, what the
+    one-member pass gives for each (the batch only adds GEMM batches)."""
+    pf, sg = _lib()
+    f = _small_fno(pf, sg, seed=3)
+    us = torch.stack([_state(pf, run=r) for r in range(3)])
+    out = torch.empty_like(us)
+    f.apply_batch(us, out)
+    for b in range(3):
+        one = torch.empty_like(us[b])
+        f.apply(us[b].contiguous(), one)
+        assert torch.equal(out[b], one), b
+
+
+def test_ensemble_advance_limits_and_untouched_members():
+    """The ensemble form of the checked advance (one batched network pass for
+    the listed members, the checks and plain intervals by the ensemble):
+    with a tolerance every check meets it is the network applied interval by
+    interval; with one no check meets it is the plain trajectory; members not
+    listed keep their state and time.  The ensemble keeps its members in
+    reciprocal space, so reading a state back goes through one inverse and
+    one forward transform: the network trajectory is compared to 1e-14 of
+    the field's largest value (round-off of that round trip)."""
+    pf, sg = _lib()
+    mem = _ens_members(pf, [N, 48, N])
+    f = _small_fno(pf, sg, seed=4)
+    kw = dict(method="ark436l", adaptive=False, dt0=DT)
+    with pf.Ensemble([dict(n=n, **kw) for n, _, _ in mem]) as E:
+        for m, (n, c, eta) in enumerate(mem):
+            E.set_state(m, c, eta)
+        before48 = E.get_state(1)
+        start = {m: E.get_state(m) for m in (0, 2)}
+        st = f.ensemble_advance(E, [0, 2], 4, DELTA, check_every=2, tol=1e300)
+        assert [(x.surrogate, x.checks, x.fallbacks, x.plain) for x in st] == [(4, 2, 0, 0)] * 2
+        for m in (0, 2):
+            v = torch.from_numpy(np.concatenate([start[m][0][None], start[m][1]])).cuda()
+            w = torch.empty_like(v)
+            for _ in range(4):
+                f.apply(v, w)
+                v, w = w, v
+            c, eta = E.get_state(m)
+            got = torch.from_numpy(np.concatenate([c[None], eta])).cuda()
+            for fld in range(4):
+                scale = float(v[fld].abs().max())
+                assert float((got[fld] - v[fld]).abs().max()) <= 1e-14 * scale, (m, fld)
+        c48, eta48 = E.get_state(1)
+        assert np.array_equal(c48, before48[0]) and np.array_equal(eta48, before48[1])
+    with pf.Ensemble([dict(n=n, **kw) for n, _, _ in mem]) as E:
+        for m, (n, c, eta) in enumerate(mem):
+            E.set_state(m, c, eta)
+        st = f.ensemble_advance(E, [0, 2], 6, DELTA, check_every=1, tol=0.0)
+        assert [(x.surrogate, x.checks, x.fallbacks, x.plain) for x in st] == [(3, 3, 3, 3)] * 2
+        for m in (0, 2):
+            with pf.Solver(N, None, **kw) as ref:
+                ref.set_state(mem[m][1], mem[m][2])
+                ref.advance(6 * DELTA)
+                want_c, want_eta = ref.get_state()
+            c, eta = E.get_state(m)
+            assert np.linalg.norm(c - want_c) <= 1e-11 * np.linalg.norm(want_c), m
+            assert np.linalg.norm(eta - want_eta) <= 1e-11 * np.linalg.norm(want_eta), m
+
+
+def test_ensemble_advance_cadence_and_arguments():
+    pf, sg = _lib()
+    mem = _ens_members(pf, [N, N], seed0=60)
+    f = _small_fno(pf, sg, seed=5)
+    kw = dict(method="ark436l", adaptive=False, dt0=DT)
+    finals = []
+    stats = []
+    for split in ((7,), (2, 1, 4)):
+        with pf.Ensemble([dict(n=n, **kw) for n, _, _ in mem]) as E:
+            for m, (n, c, eta) in enumerate(mem):
+                E.set_state(m, c, eta)
+            st = None
+            for k in split:
+                st = f.ensemble_advance(E, [0, 1], k, DELTA, check_every=3, tol=0.0, stats=st)
+            stats.append([(x.surrogate, x.checks, x.fallbacks, x.plain, x.since_check, x.plain_left) for x in st])
+            finals.append([E.get_state(m) for m in (0, 1)])
+            with pytest.raises(pf.PFError):
+                f.ensemble_advance(E, [0, 0], 1, DELTA)          # a member twice
+            with pytest.raises(pf.PFError):
+                f.ensemble_advance(E, [2], 1, DELTA)             # no such member
+    assert stats[0] == stats[1] == [(4, 1, 1, 3, 1, 0)] * 2
+    # Between calls a member's state goes through the ensemble's reciprocal-space
+    # storage (round-off); the BF16 network can turn such a difference into a
+    # changed rounding of an activation, so the two runs agree to 1e-6, not bitwise.
+    for a, b in zip(finals[0], finals[1]):
+        assert np.linalg.norm(a[0] - b[0]) <= 1e-6 * np.linalg.norm(b[0])
+        assert np.linalg.norm(a[1] - b[1]) <= 1e-6 * np.linalg.norm(b[1])
