@@ -628,9 +628,34 @@ def fno_step_bench(torch, n=128, reps=10):
     layer = 2 * P * wd * wd + 2 * (4 * m * wd * n ** 3 + 16 * m * m * wd * n * n + 32 * m ** 3 * wd * n) \
         + 32 * m ** 3 * wd * wd
     fwd = 2 * P * 8 * wd + L * layer + 2 * P * wd * h + 2 * P * h * 8
+    # algorithmic bytes and flops per kind (the library's own accounting) of
+    # one training step, one Adam step and one advance
+    work = {}
+    for name, call in (("grad", lambda: f.grad(x, y)), ("adam", lambda: f.adam_step(1e-4)),
+                       ("apply", lambda: f.apply(u, w))):
+        f.work(1)
+        call()
+        work[name] = {k: dict(gb=round(v["bytes"] / 1e9, 4), gflop=round(v["flops"] / 1e9, 3),
+                              launches=v["launches"]) for k, v in f.work(0).items() if v["launches"]}
+    torch.cuda.synchronize()
+    # batched advances: B samples through one network pass
+    batched = {}
+    for B in (1, 4, 8):
+        ub = u.unsqueeze(0).expand(B, -1, -1, -1, -1).contiguous()
+        wb = torch.empty_like(ub)
+        f.apply_batch(ub, wb)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            f.apply_batch(ub, wb)
+        torch.cuda.synchronize()
+        tb = (time.perf_counter() - t0) / reps
+        batched[str(B)] = dict(ms=round(1e3 * tb, 3), ms_per_sample=round(1e3 * tb / B, 3),
+                               tflops=round(B * fwd / tb / 1e12, 2))
+        del ub, wb
     return dict(n=n, grad_ms=round(1e3 * t_grad, 3), adam_ms=round(1e3 * t_adam, 3), apply_ms=round(1e3 * t_apply, 3),
                 forward_gflop=round(fwd / 1e9, 2),
-                apply_tflops=round(fwd / t_apply / 1e12, 2))
+                apply_tflops=round(fwd / t_apply / 1e12, 2), apply_batch=batched, work=work)
 
 
 def main():

@@ -411,6 +411,22 @@ pf_status pf_fno_train_step(pf_fno* f, const float* x, const float* y, int32_t b
  * restored (the composition is conserved); state / next device float64
  * [cin][n^3] (cin == cout); next may equal state */
 pf_status pf_fno_apply(pf_fno* f, const double* state, double* next);
+/* Work accounting of the network's kernels: with it on, every launch adds its
+ * algorithmic bytes (each operand read once and each result written once, at
+ * its storage width: BF16 activations and weights, FP32 outputs, gradients
+ * and spectra, FP64 states) and flops (2 per multiply-add) to its kind.
+ * Kinds, in this order (PF_FNO_KINDS): 0 truncated-DFT GEMMs (k_lm_gemm),
+ * 1 channel-mixing GEMMs (k_cm_gemm), 2 weight-gradient reductions
+ * (k_wgrad_mfma), 3 their partial sums (k_sum_partials), 4 per-mode mixing
+ * (k_mix_*), 5 GELU backward (k_gelu_bwd), 6 elementwise (input packing,
+ * loss, Adam, surrogate update, mass reset).  bytes / flops / launches
+ * [kinds] (host) receive the totals since the last reset (kinds beyond
+ * PF_FNO_KINDS read 0; kinds == 0 reads nothing); then enable = 1 resets the
+ * totals and turns the accounting on, enable = 0 resets and turns it off,
+ * enable < 0 leaves both.  Host-side only: no device work, no effect on
+ * results.  Errors: PF_ERR_ARG (NULL handle or arrays, kinds < 0). */
+#define PF_FNO_KINDS 7
+pf_status pf_fno_work(pf_fno* f, int32_t enable, double* bytes, double* flops, int64_t* launches, int32_t kinds);
 /* pf_fno_apply for `batch` samples at once (states / nexts device float64
  * [batch][cin][n^3]; nexts may equal states): one network pass whose GEMMs
  * run over every sample's points and lines together, so each sample's result

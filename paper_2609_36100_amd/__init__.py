@@ -451,6 +451,16 @@ class FNO:
         """out = state + scale * net(state), mean of c restored (device float64 (cin, n, n, n))."""
         _lib.check(_lib.lib().pf_fno_apply(self._h, _ptr(state), _ptr(out)), "pf_fno_apply")
 
+    WORK_KINDS = ("lm_gemm", "cm_gemm", "wgrad", "wgrad_sum", "mix", "gelu_bwd", "elementwise")
+
+    def work(self, enable=-1):
+        """Algorithmic bytes / flops / launches per kind since the last reset (pf_fno_work);
+        enable = 1 / 0 then resets and turns the accounting on / off."""
+        k = len(self.WORK_KINDS)
+        b, f, n = (ctypes.c_double * k)(), (ctypes.c_double * k)(), (ctypes.c_int64 * k)()
+        _lib.check(_lib.lib().pf_fno_work(self._h, int(enable), b, f, n, k), "pf_fno_work")
+        return {name: dict(bytes=b[i], flops=f[i], launches=n[i]) for i, name in enumerate(self.WORK_KINDS)}
+
     def apply_batch(self, states, out):
         """out[b] = states[b] + scale * net(states[b]) for every b (device float64 (B, cin, n, n, n))."""
         assert states.is_contiguous() and out.is_contiguous() and states.shape == out.shape

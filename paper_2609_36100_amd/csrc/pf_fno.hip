@@ -514,9 +514,17 @@ __global__ void __launch_bounds__(256) k_rel_l2(const double* __restrict__ a, co
 }  // namespace
 
 // ---- host side ----------------------------------------------------------------
+// Kinds of work for the accounting of algorithmic bytes and flops
+// (pf_fno_work): each launch counts its operands read once and its results
+// written once, at their storage widths.
+enum FnoKind { FK_LM = 0, FK_CM, FK_WGRAD, FK_WSUM, FK_MIX, FK_GELU, FK_ELEM, FK_COUNT };
+
 struct pf_fno {
   pf_fno_config cfg;
   hipStream_t stream = nullptr;
+  int acct = 0;  // accounting on
+  double acct_bytes[FK_COUNT] = {}, acct_flops[FK_COUNT] = {};
+  long long acct_n[FK_COUNT] = {};
   long long P = 0;
   int mode_count = 0;   // (2m)^2 m
   int cinp = 8, coutp = 8;  // padded channel counts (K % 8)
@@ -583,6 +591,13 @@ static pf_status falloc(pf_fno* F, void** p, size_t bytes) {
 
 static inline unsigned gdiv(long long n, int b) { return (unsigned)((n + b - 1) / b); }
 
+static inline void account(pf_fno* F, int kind, double bytes, double flops) {
+  if (!F->acct) return;
+  F->acct_bytes[kind] += bytes;
+  F->acct_flops[kind] += flops;
+  F->acct_n[kind] += 1;
+}
+
 // Real DFT matrices for the six stages (see the header comment of this file).
 static void build_dft(int n, int m, std::vector<std::vector<float>>& out) {
   const double pi = 3.14159265358979323846;
@@ -636,10 +651,24 @@ static pf_status upload_bf16(pf_fno* F, const std::vector<float>& h, u16** d) {
   return PF_OK;
 }
 
+// algorithmic bytes of one channel-mixing GEMM over `points` points
+static double cm_bytes(double points, int K, int N, const float* bias, const float* resid, const float* outf,
+                       const u16* outpre, const u16* outact, int accumulate) {
+  double b = points * K * 2.0 + 2.0 * N * K + (bias ? 4.0 * N : 0.0);
+  if (resid) b += points * N * 4.0;
+  if (outf) b += points * N * (accumulate ? 8.0 : 4.0);
+  if (outpre) b += points * N * 2.0;
+  if (outact) b += points * N * 2.0;
+  return b;
+}
+
 static void lm(pf_fno* F, const u16* G, int R, int K, const u16* X, long long xbs, int ldx, int Nc, int batches,
                float* outf, u16* outb, long long obs, int ldo, int accumulate) {
   const int wpb = Nc <= 32 ? 1 : (Nc <= 64 ? 2 : 4);  // waves per batch
   dim3 grid(gdiv(Nc, 32 * wpb), gdiv(batches, 4 / wpb));
+  const double cols = (double)Nc * batches;
+  account(F, FK_LM, 2.0 * R * K + 2.0 * K * cols + (outf ? (accumulate ? 8.0 : 4.0) : 2.0) * R * cols,
+          2.0 * R * K * cols);
   k_lm_gemm<<<grid, 256, 0, F->stream>>>(G, R, K, X, xbs, ldx, Nc, outf, outb, obs, ldo, accumulate, wpb,
                                          (long long)batches);
 }
@@ -647,6 +676,8 @@ static void lm(pf_fno* F, const u16* G, int R, int K, const u16* X, long long xb
 static void cm(pf_fno* F, const u16* In, int ldin, int K, const u16* Bt, int N, const float* bias, const float* resid,
                int ldres, float* outf, u16* outpre, u16* outact, int ldout, int accumulate) {
   const unsigned grid = (unsigned)(F->P / 128);
+  account(F, FK_CM, cm_bytes((double)F->P, K, N, bias, resid, outf, outpre, outact, accumulate),
+          2.0 * F->P * K * N);
   if (N <= 32)
     k_cm_gemm<1><<<grid, 256, 0, F->stream>>>(In, ldin, K, Bt, N, bias, resid, ldres, outf, outpre, outact, ldout,
                                                accumulate);
@@ -663,8 +694,27 @@ static void wgrad(pf_fno* F, const u16* A, int lda, int K, const float* D, int l
   const int nb = (int)gdiv(F->P, chunk);
   const int KN = (K + 1) * N;
   const int tiles = ((K + 31) / 32) * ((N + 31) / 32);
+  const int ntx = (N + 31) / 32;
   for (int t0 = 0; t0 < tiles; t0 += 4) {
+    // this launch's tiles: the K and N ranges it reads, the outputs it forms
+    const int t1 = std::min(tiles, t0 + 4);
+    double kk = 0.0, nn = 0.0, outs = 0.0;
+    {
+      int kmin = 1 << 30, kmax = 0, nmin = 1 << 30, nmax = 0;
+      for (int t = t0; t < t1; ++t) {
+        const int kt = t / ntx, nt = t % ntx;
+        kmin = std::min(kmin, kt * 32);
+        kmax = std::max(kmax, std::min(K, kt * 32 + 32));
+        nmin = std::min(nmin, nt * 32);
+        nmax = std::max(nmax, std::min(N, nt * 32 + 32));
+        outs += (double)(std::min(K, kt * 32 + 32) - kt * 32) * (std::min(N, nt * 32 + 32) - nt * 32);
+      }
+      kk = kmax - kmin;
+      nn = nmax - nmin;
+    }
+    account(F, FK_WGRAD, (double)F->P * (2.0 * kk + 4.0 * nn) + 4.0 * nb * KN, 2.0 * F->P * outs);
     k_wgrad_mfma<<<nb, 256, 0, F->stream>>>(A, lda, K, D, ldd, N, F->P, chunk, t0, F->part);
+    account(F, FK_WSUM, 4.0 * nb * outs + 8.0 * outs, (double)nb * outs);
     k_sum_partials<<<gdiv(KN, 64), 256, 0, F->stream>>>(F->part, nb, K, N, t0, gW, gb);
   }
 }
@@ -692,6 +742,12 @@ static void refresh(pf_fno* F) {
   cvt(F->o_P2, h, c.cout, F->coutp, c.cout, 1, F->bP2);  // P2 [h][coutp]
 }
 
+// per-mode mixing of `batches` spectra: S (f32) and R (bf16) in, T (f32) and Tb (bf16) out
+static double mix_fwd_bytes(int modes, int w, int batches) {
+  const double mo = (double)modes * w;
+  return batches * (2.0 * mo * 4.0 + 2.0 * mo * (4.0 + 2.0)) + 2.0 * modes * (double)w * w * 2.0;
+}
+
 // forward pass for the packed input F->xin; leaves the result in F->outf
 static void forward(pf_fno* F) {
   const pf_fno_config& c = F->cfg;
@@ -708,6 +764,7 @@ static void forward(pf_fno* F) {
     const int Nz = m2 * m * w;
     lm(F, F->Gzf, 2 * m2, 2 * n, F->A2, 0, Nz, Nz, 1, F->S[l], nullptr, 0, Nz, 0);
     // per-mode mixing
+    account(F, FK_MIX, mix_fwd_bytes(F->mode_count, w, 1), 8.0 * F->mode_count * w * w);
     k_mix_fwd<<<gdiv((long long)F->mode_count * w, 256), 256, 0, F->stream>>>(F->S[l], F->bRr[l], F->bRi[l], F->T,
                                                                                F->mode_count, w, F->Tb, 1);
     // inverse: z, y (batch z), x (batch z,y)
@@ -734,12 +791,14 @@ static void backward(pf_fno* F) {
   // projection: out = hact P2 + c2
   wgrad(F, F->hact, h, h, F->dvf2, co, co, g + F->o_P2, g + F->o_c2);
   cm(F, F->douthb, F->coutp, F->coutp, F->bP2, h, nullptr, nullptr, 0, F->dhf, nullptr, nullptr, h, 0);
+  account(F, FK_GELU, (double)P * h * (4.0 + 2.0 + 4.0 + 2.0), 20.0 * P * h);
   k_gelu_bwd<<<gdiv(P * h, 256), 256, 0, F->stream>>>(F->dhf, F->hpre, F->dhf, F->dhb, P * h, 0);
   wgrad(F, F->pre[c.layers - 1], w, w, F->dhf, h, h, g + F->o_P1, g + F->o_c1);
   cm(F, F->dhb, h, h, F->bP1, w, nullptr, nullptr, 0, F->dvf, nullptr, nullptr, w, 0);
   const int Nz = m2 * m * w;
   for (int l = c.layers - 1; l >= 0; --l) {
     const bool last = l == c.layers - 1;
+    account(F, FK_GELU, (double)P * w * (4.0 + 2.0 + 4.0 + 2.0), 20.0 * P * w);
     k_gelu_bwd<<<gdiv(P * w, 256), 256, 0, F->stream>>>(F->dvf, F->pre[l], F->dpref, F->dpreb, P * w, last ? 1 : 0);
     wgrad(F, F->v[l], w, w, F->dpref, w, w, g + F->o_W[l], g + F->o_b[l]);
     // pointwise data gradient
@@ -749,6 +808,10 @@ static void backward(pf_fno* F) {
     lm(F, F->GyiT, 2 * m2, 2 * n, F->B2, (long long)2 * n * m * w, m * w, m * w, n, nullptr, F->B3,
        (long long)2 * m2 * m * w, m * w, 0);
     lm(F, F->GziT, 2 * m2, 2 * n, F->B3, 0, Nz, Nz, 1, F->dT, nullptr, 0, Nz, 0);
+    account(F, FK_MIX, 2.0 * F->mode_count * w * 4.0 * 2 + 2.0 * F->mode_count * (double)w * w * 8.0,
+            8.0 * F->mode_count * w * w);
+    account(F, FK_MIX, 2.0 * F->mode_count * w * (4.0 + 2.0) + 2.0 * F->mode_count * (double)w * w * 2.0,
+            8.0 * F->mode_count * w * w);
     k_mix_bwd_w<<<gdiv((long long)F->mode_count * w * w, 256), 256, 0, F->stream>>>(
         F->S[l], F->dT, g + F->o_Rr[l], g + F->o_Ri[l], F->mode_count, w);
     k_mix_bwd_data<<<gdiv((long long)F->mode_count * w, 256), 256, 0, F->stream>>>(F->dT, F->bRr[l], F->bRi[l],
@@ -980,6 +1043,7 @@ pf_status pf_fno_set_input_norm(pf_fno* F, const float* shift, const float* scal
 
 pf_status pf_fno_forward(pf_fno* F, const float* x, float* out) {
   if (!F || !x || !out) return PF_ERR_ARG;
+  account(F, FK_ELEM, (double)F->P * (4.0 * F->cfg.cin + 2.0 * F->cinp), 0.0);
   k_pack_input<float><<<gdiv(F->P, 256), 256, 0, F->stream>>>(x, F->P, F->cfg.cin, F->cinp, F->innorm, F->xin);
   forward(F);
   FH(hipMemcpyAsync(out, F->outf, 4 * F->P * F->cfg.cout, hipMemcpyDeviceToDevice, F->stream));
@@ -990,9 +1054,11 @@ pf_status pf_fno_forward(pf_fno* F, const float* x, float* out) {
 
 pf_status pf_fno_grad(pf_fno* F, const float* x, const float* y, double* loss) {
   if (!F || !x || !y) return PF_ERR_ARG;
+  account(F, FK_ELEM, (double)F->P * (4.0 * F->cfg.cin + 2.0 * F->cinp), 0.0);
   k_pack_input<float><<<gdiv(F->P, 256), 256, 0, F->stream>>>(x, F->P, F->cfg.cin, F->cinp, F->innorm, F->xin);
   forward(F);
   const unsigned nb = gdiv(F->P, 256);
+  account(F, FK_ELEM, (double)F->P * F->cfg.cout * (4.0 * 4) + (double)F->P * F->coutp * 2.0, 0.0);
   k_loss<<<nb, 256, 0, F->stream>>>(F->outf, x, y, F->scale, F->P, F->cfg.cout, F->coutp, F->dvf2, F->douthb,
                                     F->dpart);
   k_sum_d<<<1, 256, 0, F->stream>>>(F->dpart, (int)nb, F->dsum);
@@ -1008,6 +1074,7 @@ pf_status pf_fno_adam_step(pf_fno* F, float lr, float beta1, float beta2, float 
   if (!F) return PF_ERR_ARG;
   F->adam_t += 1;
   const float c1 = 1.f - powf(beta1, (float)F->adam_t), c2 = 1.f - powf(beta2, (float)F->adam_t);
+  account(F, FK_ELEM, 7.0 * 4.0 * F->nparams, 0.0);
   k_adam<<<gdiv(F->nparams, 256), 256, 0, F->stream>>>(F->th, F->am, F->av, F->gr, F->nparams, lr, beta1, beta2,
                                                        eps, grad_scale, c1, c2);
   refresh(F);
@@ -1156,6 +1223,7 @@ static void cm_points(pf_fno* F, long long points, const u16* In, int ldin, int 
                       const float* bias, const float* resid, int ldres, float* outf, u16* outpre, u16* outact,
                       int ldout) {
   const unsigned grid = (unsigned)(points / 128);
+  account(F, FK_CM, cm_bytes((double)points, K, N, bias, resid, outf, outpre, outact, 0), 2.0 * points * K * N);
   if (N <= 32)
     k_cm_gemm<1><<<grid, 256, 0, F->stream>>>(In, ldin, K, Bt, N, bias, resid, ldres, outf, outpre, outact, ldout, 0);
   else
@@ -1180,6 +1248,7 @@ static void forward_batch(pf_fno* F, int B) {
     lm(F, F->Gyf, 2 * m2, 2 * n, F->bA1, (long long)n * 2 * m * w, m * w, m * w, B * n, nullptr, F->bA2,
        (long long)2 * m2 * m * w, m * w, 0);
     lm(F, F->Gzf, 2 * m2, 2 * n, F->bA2, 2LL * n * Nz, (int)Nz, (int)Nz, B, F->bS, nullptr, spec, (int)Nz, 0);
+    account(F, FK_MIX, mix_fwd_bytes(F->mode_count, w, B), 8.0 * F->mode_count * w * w * B);
     k_mix_fwd<<<gdiv((long long)F->mode_count * w * B, 256), 256, 0, F->stream>>>(F->bS, F->bRr[l], F->bRi[l],
                                                                                    F->bT, F->mode_count, w,
                                                                                    F->bTb, B);
@@ -1204,15 +1273,19 @@ static pf_status apply_batch(pf_fno* F, const double* states, double* nexts, int
   const long long P = F->P;
   const int ci = F->cfg.cin, co = F->cfg.cout;
   const unsigned nb = gdiv(P, 256);
-  for (int b = 0; b < B; ++b)
+  for (int b = 0; b < B; ++b) {
+    account(F, FK_ELEM, (double)P * (8.0 * ci + 2.0 * F->cinp), 0.0);
     k_pack_input<double><<<nb, 256, 0, F->stream>>>(states + (long long)b * ci * P, P, ci, F->cinp, F->innorm,
                                                     F->bxin + (long long)b * P * F->cinp);
+  }
   forward_batch(F, B);
   for (int b = 0; b < B; ++b) {
     double* nx = nexts + (long long)b * co * P;
+    account(F, FK_ELEM, (double)P * co * (8.0 + 4.0 + 8.0), 0.0);
     k_apply<<<nb, 256, 0, F->stream>>>(states + (long long)b * ci * P, F->boutf + (long long)b * P * co, F->scale, P,
                                        co, nx, F->bdpart + (long long)b * nb);
     k_sum_d<<<1, 256, 0, F->stream>>>(F->bdpart + (long long)b * nb, (int)nb, F->bdsum + b);
+    account(F, FK_ELEM, (double)P * 16.0, 0.0);
     k_shift<<<nb, 256, 0, F->stream>>>(nx, P, F->bdsum + b);
   }
   FH(hipGetLastError());
@@ -1222,6 +1295,27 @@ static pf_status apply_batch(pf_fno* F, const double* states, double* nexts, int
 
 extern "C" {
 
+pf_status pf_fno_work(pf_fno* F, int32_t enable, double* bytes, double* flops, int64_t* launches, int32_t kinds) {
+  if (!F || kinds < 0 || (kinds > 0 && (!bytes || !flops || !launches))) return PF_ERR_ARG;
+  for (int k = 0; k < kinds && k < FK_COUNT; ++k) {
+    bytes[k] = F->acct_bytes[k];
+    flops[k] = F->acct_flops[k];
+    launches[k] = F->acct_n[k];
+  }
+  for (int k = FK_COUNT; k < kinds; ++k) {
+    bytes[k] = flops[k] = 0.0;
+    launches[k] = 0;
+  }
+  if (enable >= 0) {
+    F->acct = enable ? 1 : 0;
+    for (int k = 0; k < FK_COUNT; ++k) {
+      F->acct_bytes[k] = F->acct_flops[k] = 0.0;
+      F->acct_n[k] = 0;
+    }
+  }
+  return PF_OK;
+}
+
 pf_status pf_fno_apply_batch(pf_fno* F, const double* states, double* nexts, int32_t batch) {
   if (!F || !states || !nexts || batch < 1 || F->cfg.cin != F->cfg.cout) return PF_ERR_ARG;
   return apply_batch(F, states, nexts, batch);
@@ -1229,11 +1323,14 @@ pf_status pf_fno_apply_batch(pf_fno* F, const double* states, double* nexts, int
 
 pf_status pf_fno_apply(pf_fno* F, const double* state, double* next) {
   if (!F || !state || !next || F->cfg.cin != F->cfg.cout) return PF_ERR_ARG;
+  account(F, FK_ELEM, (double)F->P * (8.0 * F->cfg.cin + 2.0 * F->cinp), 0.0);
   k_pack_input<double><<<gdiv(F->P, 256), 256, 0, F->stream>>>(state, F->P, F->cfg.cin, F->cinp, F->innorm, F->xin);
   forward(F);
   const unsigned nb = gdiv(F->P, 256);
+  account(F, FK_ELEM, (double)F->P * F->cfg.cout * (8.0 + 4.0 + 8.0), 0.0);
   k_apply<<<nb, 256, 0, F->stream>>>(state, F->outf, F->scale, F->P, F->cfg.cout, next, F->dpart);
   k_sum_d<<<1, 256, 0, F->stream>>>(F->dpart, (int)nb, F->dsum);
+  account(F, FK_ELEM, (double)F->P * 16.0, 0.0);
   k_shift<<<nb, 256, 0, F->stream>>>(next, F->P, F->dsum);
   FH(hipGetLastError());
   FH(hipStreamSynchronize(F->stream));

@@ -230,3 +230,37 @@ def test_load_float32_and_bfloat16_weights():
         assert np.array_equal(f.get_params(), widened)
         with pytest.raises(PFError):
             f.load(theta[:-1])
+
+
+def test_work_accounting_counts_the_network():
+    """pf_fno_work: one advance is 6 truncated-DFT GEMMs, one channel-mixing
+    GEMM and one per-mode mixing per layer plus lift and the two projection
+    GEMMs; their flops are those of the network's shapes (x stage 4 m w n^3,
+    y 16 m^2 w n^2, z 32 m^3 w n each way per layer; channel mixing 2 P K N
+    with the input padded to 8 channels; mixing 8 w^2 per retained mode), and
+    accounting off counts nothing."""
+    import torch
+    from paper_2609_36100_amd import FNO
+    _say("fno work accounting")
+    n, w, m, L, h = 32, 8, 4, 2, 16
+    P = n ** 3
+    net = of.FNO(n, width=w, modes=m, layers=L, hidden=h)
+    rng = np.random.default_rng(3)
+    u = torch.from_numpy(rng.uniform(0, 1, (4, n, n, n))).cuda()
+    v = torch.empty_like(u)
+    with FNO(n, width=w, modes=m, layers=L, hidden=h) as f:
+        f.set_params(_flat(net, net.init_params(seed=4)))
+        f.work(1)
+        f.apply(u, v)
+        wk = f.work(0)
+        f.apply(u, v)
+        assert all(x["launches"] == 0 for x in f.work(-1).values())
+    assert wk["lm_gemm"]["launches"] == 6 * L
+    assert wk["cm_gemm"]["launches"] == L + 3
+    assert wk["mix"]["launches"] == L
+    assert wk["lm_gemm"]["flops"] == L * 2 * (4 * m * w * n ** 3 + 16 * m * m * w * n * n + 32 * m ** 3 * w * n)
+    assert wk["cm_gemm"]["flops"] == 2 * P * (8 * w + L * w * w + w * h + h * 4)
+    assert wk["mix"]["flops"] == L * 8 * (4 * m ** 3) * w * w
+    # every GEMM reads its activations at least once: the channel-mixing bytes
+    # cover the BF16 inputs of lift, the layers and both projections
+    assert wk["cm_gemm"]["bytes"] > 2 * P * (8 + L * w + w + h)
