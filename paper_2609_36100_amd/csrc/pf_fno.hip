@@ -69,14 +69,27 @@ __device__ inline float gelu_g(float x) {
 
 __device__ inline bf16x4 ld4(const u16* p) { return *reinterpret_cast<const bf16x4*>(p); }
 
-// ---- channel-mixing GEMM: Out[p][n] = epi(sum_k In[p][k] Bt[n][k]) ----------
+// A second contraction along the x lines that a channel-mixing GEMM can carry:
+// for point p = line * R + x, adds sum_k G[x][k] X[line * xbs + k * ldx + n]
+// (the truncated-DFT x stage whose result the GEMM would otherwise read back
+// as a residual).  G row-major R x K (K % 4 == 0, zero beyond K); R % 32 == 0
+// so that a wave's 32 points lie in one line.  G == nullptr: none.
+struct LineTerm {
+  const u16* G = nullptr;
+  int K = 0, R = 0;
+  const u16* X = nullptr;
+  long long xbs = 0;
+  int ldx = 0;
+};
+
+// ---- channel-mixing GEMM: Out[p][n] = epi(sum_k In[p][k] Bt[n][k] [+ line term]) ----
 // K % 4 == 0 (zero beyond K), P % 128 == 0, N <= 32 * NT.  Epilogue: + bias[n] + resid[p][n],
 // stores any of: f32 result, bf16 pre-activation, bf16 GELU(pre).
 template <int NT>
 __global__ void __launch_bounds__(256)
 k_cm_gemm(const u16* __restrict__ In, int ldin, int K, const u16* __restrict__ Bt, int N,
           const float* __restrict__ bias, const float* __restrict__ resid, int ldres, float* __restrict__ outf,
-          u16* __restrict__ outpre, u16* __restrict__ outact, int ldout, int accumulate) {
+          u16* __restrict__ outpre, u16* __restrict__ outact, int ldout, int accumulate, LineTerm lt) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const long long p0 = ((long long)blockIdx.x * 4 + wave) * 32;
   const int lr = lane & 31, lg = lane >> 5;
@@ -99,6 +112,32 @@ k_cm_gemm(const u16* __restrict__ In, int ldin, int K, const u16* __restrict__ B
       if (n < N && in0) b0 = ld4(Bt + (long long)n * K + kb);
       if (n < N && in1) b1 = ld4(Bt + (long long)n * K + kb + 4);
       acc[t] = mfma16(a0, a1, b0, b1, acc[t]);
+    }
+  }
+  if (lt.G) {
+    const long long line = p0 / lt.R;
+    const int x = (int)(p0 % lt.R) + lr;
+    const u16* Xb = lt.X + line * lt.xbs;
+    for (int kk = 0; kk < lt.K; kk += 16) {
+      const int kb = kk + lg * 8;
+      const bool in0 = kb < lt.K, in1 = kb + 4 < lt.K;
+      bf16x4 a0 = {0, 0, 0, 0}, a1 = {0, 0, 0, 0};
+      if (in0) a0 = ld4(lt.G + (long long)x * lt.K + kb);
+      if (in1) a1 = ld4(lt.G + (long long)x * lt.K + kb + 4);
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        const int n = t * 32 + lr;
+        bf16x4 b0 = {0, 0, 0, 0}, b1 = {0, 0, 0, 0};
+        if (n < N && in0) {
+#pragma unroll
+          for (int j = 0; j < 4; ++j) b0[j] = (short)Xb[(long long)(kb + j) * lt.ldx + n];
+        }
+        if (n < N && in1) {
+#pragma unroll
+          for (int j = 0; j < 4; ++j) b1[j] = (short)Xb[(long long)(kb + 4 + j) * lt.ldx + n];
+        }
+        acc[t] = mfma16(a0, a1, b0, b1, acc[t]);
+      }
     }
   }
 #pragma unroll
@@ -523,6 +562,7 @@ struct pf_fno {
   pf_fno_config cfg;
   hipStream_t stream = nullptr;
   int acct = 0;  // accounting on
+  bool fuse_x = false;  // x stages carried by the channel-mixing GEMMs (n % 32 == 0)
   double acct_bytes[FK_COUNT] = {}, acct_flops[FK_COUNT] = {};
   long long acct_n[FK_COUNT] = {};
   long long P = 0;
@@ -673,17 +713,29 @@ static void lm(pf_fno* F, const u16* G, int R, int K, const u16* X, long long xb
                                          (long long)batches);
 }
 
-static void cm(pf_fno* F, const u16* In, int ldin, int K, const u16* Bt, int N, const float* bias, const float* resid,
-               int ldres, float* outf, u16* outpre, u16* outact, int ldout, int accumulate) {
-  const unsigned grid = (unsigned)(F->P / 128);
-  account(F, FK_CM, cm_bytes((double)F->P, K, N, bias, resid, outf, outpre, outact, accumulate),
-          2.0 * F->P * K * N);
+static void cm_launch(pf_fno* F, long long points, const u16* In, int ldin, int K, const u16* Bt, int N,
+                      const float* bias, const float* resid, int ldres, float* outf, u16* outpre, u16* outact,
+                      int ldout, int accumulate, const LineTerm& lt) {
+  const unsigned grid = (unsigned)(points / 128);
+  double bytes = cm_bytes((double)points, K, N, bias, resid, outf, outpre, outact, accumulate);
+  double flops = 2.0 * points * K * N;
+  if (lt.G) {
+    bytes += 2.0 * lt.R * lt.K + (double)(points / lt.R) * lt.K * N * 2.0;
+    flops += 2.0 * points * lt.K * N;
+  }
+  account(F, FK_CM, bytes, flops);
   if (N <= 32)
     k_cm_gemm<1><<<grid, 256, 0, F->stream>>>(In, ldin, K, Bt, N, bias, resid, ldres, outf, outpre, outact, ldout,
-                                               accumulate);
+                                               accumulate, lt);
   else
     k_cm_gemm<4><<<grid, 256, 0, F->stream>>>(In, ldin, K, Bt, N, bias, resid, ldres, outf, outpre, outact, ldout,
-                                               accumulate);
+                                               accumulate, lt);
+}
+
+static void cm(pf_fno* F, const u16* In, int ldin, int K, const u16* Bt, int N, const float* bias, const float* resid,
+               int ldres, float* outf, u16* outpre, u16* outact, int ldout, int accumulate,
+               const LineTerm& lt = LineTerm()) {
+  cm_launch(F, F->P, In, ldin, K, Bt, N, bias, resid, ldres, outf, outpre, outact, ldout, accumulate, lt);
 }
 
 constexpr int kWgradBlocks = 512;  // blocks (point chunks) of one weight-gradient reduction
@@ -748,6 +800,19 @@ static double mix_fwd_bytes(int modes, int w, int batches) {
   return batches * (2.0 * mo * 4.0 + 2.0 * mo * (4.0 + 2.0)) + 2.0 * modes * (double)w * w * 2.0;
 }
 
+// the inverse x stage of a layer's spectral path as a line term (B2: the
+// inverse y stage's output, one 2m x w block per x line)
+static LineTerm x_inverse(const pf_fno* F, const u16* B2) {
+  LineTerm lt;
+  lt.G = F->Gxi;
+  lt.K = 2 * F->cfg.modes;
+  lt.R = F->cfg.n;
+  lt.X = B2;
+  lt.xbs = (long long)2 * F->cfg.modes * F->cfg.width;
+  lt.ldx = F->cfg.width;
+  return lt;
+}
+
 // forward pass for the packed input F->xin; leaves the result in F->outf
 static void forward(pf_fno* F) {
   const pf_fno_config& c = F->cfg;
@@ -771,10 +836,17 @@ static void forward(pf_fno* F) {
     lm(F, F->Gzi, 2 * n, 2 * m2, F->Tb, 0, Nz, Nz, 1, nullptr, F->B3, 0, Nz, 0);
     lm(F, F->Gyi, 2 * n, 2 * m2, F->B3, (long long)2 * m2 * m * w, m * w, m * w, n, nullptr, F->B2,
        (long long)2 * n * m * w, m * w, 0);
-    lm(F, F->Gxi, n, 2 * m, F->B2, (long long)2 * m * w, w, w, n * n, F->B1, nullptr, (long long)n * w, w, 0);
-    // pointwise path, bias, residual spectral part, activation (the last layer is linear)
+    // pointwise path, bias, the spectral part's inverse x stage (carried by the
+    // channel-mixing GEMM when a wave's points lie in one line, else through
+    // B1), activation (the last layer is linear)
     const bool last = l == c.layers - 1;
-    cm(F, v, w, w, F->bWT[l], w, th + F->o_b[l], F->B1, w, nullptr, F->pre[l], last ? nullptr : F->v[l + 1], w, 0);
+    if (F->fuse_x) {
+      cm(F, v, w, w, F->bWT[l], w, th + F->o_b[l], nullptr, 0, nullptr, F->pre[l], last ? nullptr : F->v[l + 1], w, 0,
+         x_inverse(F, F->B2));
+    } else {
+      lm(F, F->Gxi, n, 2 * m, F->B2, (long long)2 * m * w, w, w, n * n, F->B1, nullptr, (long long)n * w, w, 0);
+      cm(F, v, w, w, F->bWT[l], w, th + F->o_b[l], F->B1, w, nullptr, F->pre[l], last ? nullptr : F->v[l + 1], w, 0);
+    }
   }
   const u16* vL = F->pre[c.layers - 1];  // v_L = pre_{L-1}
   cm(F, vL, w, w, F->bP1T, h, th + F->o_c1, nullptr, 0, nullptr, F->hpre, F->hact, h, 0);
@@ -801,8 +873,6 @@ static void backward(pf_fno* F) {
     account(F, FK_GELU, (double)P * w * (4.0 + 2.0 + 4.0 + 2.0), 20.0 * P * w);
     k_gelu_bwd<<<gdiv(P * w, 256), 256, 0, F->stream>>>(F->dvf, F->pre[l], F->dpref, F->dpreb, P * w, last ? 1 : 0);
     wgrad(F, F->v[l], w, w, F->dpref, w, w, g + F->o_W[l], g + F->o_b[l]);
-    // pointwise data gradient
-    cm(F, F->dpreb, w, w, F->bW[l], w, nullptr, nullptr, 0, F->dvf, nullptr, nullptr, w, 0);
     // spectral path: transposes of the inverse stages
     lm(F, F->GxiT, 2 * m, n, F->dpreb, (long long)n * w, w, w, n * n, nullptr, F->B2, (long long)2 * m * w, w, 0);
     lm(F, F->GyiT, 2 * m2, 2 * n, F->B2, (long long)2 * n * m * w, m * w, m * w, n, nullptr, F->B3,
@@ -820,7 +890,20 @@ static void backward(pf_fno* F) {
     lm(F, F->GzfT, 2 * n, 2 * m2, F->dSb, 0, Nz, Nz, 1, nullptr, F->A2, 0, Nz, 0);
     lm(F, F->GyfT, 2 * n, 2 * m2, F->A2, (long long)2 * m2 * m * w, m * w, m * w, n, nullptr, F->A1,
        (long long)2 * n * m * w, m * w, 0);
-    lm(F, F->GxfT, n, 2 * m, F->A1, (long long)2 * m * w, w, w, n * n, F->dvf, nullptr, (long long)n * w, w, 1);
+    // pointwise data gradient plus the transposed x stage of the spectral path
+    if (F->fuse_x) {
+      LineTerm lt;
+      lt.G = F->GxfT;
+      lt.K = 2 * m;
+      lt.R = n;
+      lt.X = F->A1;
+      lt.xbs = (long long)2 * m * w;
+      lt.ldx = w;
+      cm(F, F->dpreb, w, w, F->bW[l], w, nullptr, nullptr, 0, F->dvf, nullptr, nullptr, w, 0, lt);
+    } else {
+      cm(F, F->dpreb, w, w, F->bW[l], w, nullptr, nullptr, 0, F->dvf, nullptr, nullptr, w, 0);
+      lm(F, F->GxfT, n, 2 * m, F->A1, (long long)2 * m * w, w, w, n * n, F->dvf, nullptr, (long long)n * w, w, 1);
+    }
   }
   // lift: v0 = x W_lift + b_lift
   wgrad(F, F->xin, F->cinp, c.cin, F->dvf, w, w, g + F->o_Wl, g + F->o_bl);
@@ -846,6 +929,7 @@ pf_status pf_fno_create(const pf_fno_config* cfg, void* stream, pf_fno** out) {
   for (int i = 0; i < 8; ++i) F->innorm.shift[i] = 0.f, F->innorm.inv[i] = 1.f;
   const int w = c.width, m = c.modes, m2 = 2 * m, h = c.hidden, n = c.n;
   F->mode_count = m2 * m2 * m;
+  F->fuse_x = n % 32 == 0;
   // parameter layout (same order as the oracle)
   long long off = 0;
   F->o_Wl = off; off += (long long)c.cin * w;
@@ -906,7 +990,7 @@ pf_status pf_fno_create(const pf_fno_config* cfg, void* stream, pf_fno** out) {
   A((void**)&F->T, 4 * spec);
   A((void**)&F->B3, 2 * std::max((size_t)2 * n * m2 * m * w, a2));
   A((void**)&F->B2, 2 * std::max(b2, a1));
-  A((void**)&F->B1, 4 * P * w);
+  if (!F->fuse_x) A((void**)&F->B1, 4 * P * w);
   A((void**)&F->outf, 4 * P * c.cout);
   A((void**)&F->dvf, 4 * P * w);
   A((void**)&F->dvf2, 4 * P * c.cout);
@@ -1205,7 +1289,7 @@ static pf_status ensure_batch(pf_fno* F, int B) {
   A((void**)&F->bTb, Bs * 2 * spec);
   A((void**)&F->bB3, Bs * 2 * 2 * n * Nz);
   A((void**)&F->bB2, Bs * 2 * a1);
-  A((void**)&F->bB1, Bs * 4 * P * w);
+  if (!F->fuse_x) A((void**)&F->bB1, Bs * 4 * P * w);
   A((void**)&F->bhact, Bs * 2 * P * h);
   A((void**)&F->boutf, Bs * 4 * P * c.cout);
   A((void**)&F->bdpart, Bs * 8 * gdiv(F->P, 256));
@@ -1221,13 +1305,8 @@ static pf_status ensure_batch(pf_fno* F, int B) {
 
 static void cm_points(pf_fno* F, long long points, const u16* In, int ldin, int K, const u16* Bt, int N,
                       const float* bias, const float* resid, int ldres, float* outf, u16* outpre, u16* outact,
-                      int ldout) {
-  const unsigned grid = (unsigned)(points / 128);
-  account(F, FK_CM, cm_bytes((double)points, K, N, bias, resid, outf, outpre, outact, 0), 2.0 * points * K * N);
-  if (N <= 32)
-    k_cm_gemm<1><<<grid, 256, 0, F->stream>>>(In, ldin, K, Bt, N, bias, resid, ldres, outf, outpre, outact, ldout, 0);
-  else
-    k_cm_gemm<4><<<grid, 256, 0, F->stream>>>(In, ldin, K, Bt, N, bias, resid, ldres, outf, outpre, outact, ldout, 0);
+                      int ldout, const LineTerm& lt = LineTerm()) {
+  cm_launch(F, points, In, ldin, K, Bt, N, bias, resid, ldres, outf, outpre, outact, ldout, 0, lt);
 }
 
 // The forward pass of B samples at once (inputs packed in bxin, outputs in
@@ -1255,10 +1334,16 @@ static void forward_batch(pf_fno* F, int B) {
     lm(F, F->Gzi, 2 * n, 2 * m2, F->bTb, spec, (int)Nz, (int)Nz, B, nullptr, F->bB3, 2LL * n * Nz, (int)Nz, 0);
     lm(F, F->Gyi, 2 * n, 2 * m2, F->bB3, (long long)2 * m2 * m * w, m * w, m * w, B * n, nullptr, F->bB2,
        (long long)2 * n * m * w, m * w, 0);
-    lm(F, F->Gxi, n, 2 * m, F->bB2, (long long)2 * m * w, w, w, B * n * n, F->bB1, nullptr, (long long)n * w, w, 0);
     const bool last = l == c.layers - 1;
-    cm_points(F, PB, v, w, w, F->bWT[l], w, th + F->o_b[l], F->bB1, w, nullptr, last ? vn : nullptr,
-              last ? nullptr : vn, w);
+    if (F->fuse_x) {
+      cm_points(F, PB, v, w, w, F->bWT[l], w, th + F->o_b[l], nullptr, 0, nullptr, last ? vn : nullptr,
+                last ? nullptr : vn, w, x_inverse(F, F->bB2));
+    } else {
+      lm(F, F->Gxi, n, 2 * m, F->bB2, (long long)2 * m * w, w, w, B * n * n, F->bB1, nullptr, (long long)n * w, w,
+         0);
+      cm_points(F, PB, v, w, w, F->bWT[l], w, th + F->o_b[l], F->bB1, w, nullptr, last ? vn : nullptr,
+                last ? nullptr : vn, w);
+    }
     std::swap(v, vn);
   }
   cm_points(F, PB, v, w, w, F->bP1T, h, th + F->o_c1, nullptr, 0, nullptr, nullptr, F->bhact, h);

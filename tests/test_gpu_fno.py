@@ -233,8 +233,9 @@ def test_load_float32_and_bfloat16_weights():
 
 
 def test_work_accounting_counts_the_network():
-    """pf_fno_work: one advance is 6 truncated-DFT GEMMs, one channel-mixing
-    GEMM and one per-mode mixing per layer plus lift and the two projection
+    """pf_fno_work: one advance is 5 truncated-DFT GEMMs (the inverse x stage
+    carried by the channel-mixing GEMM at n = 32), one channel-mixing GEMM
+    and one per-mode mixing per layer plus lift and the two projection
     GEMMs; their flops are those of the network's shapes (x stage 4 m w n^3,
     y 16 m^2 w n^2, z 32 m^3 w n each way per layer; channel mixing 2 P K N
     with the input padded to 8 channels; mixing 8 w^2 per retained mode), and
@@ -255,11 +256,13 @@ def test_work_accounting_counts_the_network():
         wk = f.work(0)
         f.apply(u, v)
         assert all(x["launches"] == 0 for x in f.work(-1).values())
-    assert wk["lm_gemm"]["launches"] == 6 * L
+    # with n % 32 == 0 the inverse x stage rides on the layer's channel-mixing GEMM
+    x_inv = L * 4 * m * w * n ** 3
+    assert wk["lm_gemm"]["launches"] == 5 * L
     assert wk["cm_gemm"]["launches"] == L + 3
     assert wk["mix"]["launches"] == L
-    assert wk["lm_gemm"]["flops"] == L * 2 * (4 * m * w * n ** 3 + 16 * m * m * w * n * n + 32 * m ** 3 * w * n)
-    assert wk["cm_gemm"]["flops"] == 2 * P * (8 * w + L * w * w + w * h + h * 4)
+    assert wk["lm_gemm"]["flops"] == L * 2 * (4 * m * w * n ** 3 + 16 * m * m * w * n * n + 32 * m ** 3 * w * n) - x_inv
+    assert wk["cm_gemm"]["flops"] == 2 * P * (8 * w + L * w * w + w * h + h * 4) + x_inv
     assert wk["mix"]["flops"] == L * 8 * (4 * m ** 3) * w * w
     # every GEMM reads its activations at least once: the channel-mixing bytes
     # cover the BF16 inputs of lift, the layers and both projections
