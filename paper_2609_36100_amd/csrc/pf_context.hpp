@@ -198,6 +198,7 @@ struct pf_ctx {
   bool inhom = false;      // Reuss-averaged stiffness, Hu-Chen iteration (elastic_inhom = 1)
   pf::cx<double>* E6 = nullptr;  // inhom: six strain / polarisation spectra
   double* R6 = nullptr;          // inhom: six real strain fields
+  double* LC6 = nullptr;         // inhom: the polarisation's per-point coefficients (six real fields)
   double* elmax = nullptr;       // inhom: largest strain change of the last update
   double* el_part = nullptr;     // inhom: per-block elastic energy sums
 

@@ -17,11 +17,13 @@
 //
 // Passes of one right-hand side (T1: the state after its inverse z and y
 // transforms; E6: six strain / polarisation spectra; R6: the six real strain
-// fields, tensor components xx, yy, zz, yz, xz, xy):
+// fields, tensor components xx, yy, zz, yz, xz, xy; LC6: six real fields of
+// per-point coefficients):
 //   x theta -> y, z forward (3)            theta~
 //   k_el_start        theta~ -> Gamma0 C0 eps*(theta~) into E6, F^E_c
+//   x_el_local        T1 eta -> LC6 (the polarisation's per-point coefficients)
 //   z, y inverse (6) -> x_el_strain        R6 = eps_u
-//   repeat:  x_el_tau (T1 eta, R6 -> E6), y, z forward (6), k_el_gamma (E6),
+//   repeat:  x_el_tau (LC6, R6 -> E6), y, z forward (6), k_el_gamma (E6),
 //            z, y inverse (6), x_el_strain (E6 -> R6, largest change)
 //   x_el_drive (T1, R6 -> T3 g) -> y forward, z forward to F^E_eta
 #pragma once
@@ -244,13 +246,71 @@ __device__ inline void row_eta3(const cx<double>* st, long long rb, bool rvalid,
   for (int v = 0; v < 3; ++v) row_c2r<double, M, RB>(st + (1 + v) * g.fs + rb, rvalid, et[v], bf, rbuf, twN, twM);
 }
 
-// Polarisation rows: tau = C0 eps* - (C(r) - C0)(eps_bar + eps_u - eps*), from
-// the order parameters (rows of T1) and the real strain r6, r2c of each of
-// its six tensor components into e6.
+// The per-point coefficients of the polarisation, once per solve: with
+// d = eps_bar + eps_u - eps* and C(r) - C0 = (d11, d12, d44) in Voigt form,
+//   tau_j = C0 eps*_j - d11 d_j - d12 (d_k + d_l)     (normal; k, l the other axes)
+//         = A_j - d11 u_j - d12 (u_k + u_l),
+//   A_j   = (C0 eps*)_j + d11 (eps*_j - eps_bar_j) + d12 (eps*_k + eps*_l - eps_bar_k - eps_bar_l),
+//   tau_s = -2 d44 u_s                                 (shear, tensor components),
+// so an update does no division.  Written as six real fields A_0, A_1, A_2,
+// d11, d12, d44 in the layout of the real strain (pairs of consecutive x),
+// from the c2r of the order parameters of T1.
 template <int M, int RB>
 __global__ void __launch_bounds__((RowGeo<M, RB>::THREADS))
-k_el_tau(const cx<double>* __restrict__ st, const double* __restrict__ r6, cx<double>* __restrict__ e6, Geo g,
-         ModelK m, const cx<double>* twN, const cx<double>* twM) {
+k_el_local(const cx<double>* __restrict__ st, double* __restrict__ lc6, Geo g, ModelK m, const cx<double>* twN,
+           const cx<double>* twM) {
+  using RG = RowGeo<M, RB>;
+  __shared__ cx<double> lds[RB * RG::LD];
+  const int rl = threadIdx.x / RG::TL;
+  const int bf = threadIdx.x % RG::TL;
+  const int row = blockIdx.x * RB + rl;
+  const int nrows = g.nz * g.ny;
+  const bool rvalid = row < nrows;
+  cx<double>* rbuf = lds + rl * RG::LD;
+  const long long rr = rvalid ? row : 0;
+  const long long npair = (long long)nrows * M;
+  cx<double> th[3][RG::R0];
+#pragma unroll
+  for (int v = 0; v < 3; ++v) {
+    row_c2r<double, M, RB>(st + (1 + v) * g.fs + rr * g.P, rvalid, th[v], bf, rbuf, twN, twM);
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  if (!rvalid) return;
+  cx<double>* out = reinterpret_cast<cx<double>*>(lc6) + rr * M;
+#pragma unroll
+  for (int t = 0; t < RG::R0; ++t) {
+    double o[2][6];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const double t0 = hfun(h ? th[0][t].im : th[0][t].re);
+      const double t1 = hfun(h ? th[1][t].im : th[1][t].re);
+      const double t2 = hfun(h ? th[2][t].im : th[2][t].re);
+      const Cubic C = local_stiffness(m, t0 + t1 + t2);
+      const double d11 = C.c11 - m.C0[0], d12 = C.c12 - m.C0[1], d44 = C.c44 - m.C0[2];
+      double es[3];
+      eigen_diag(m, t0, t1, t2, es);
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        const int k = (j + 1) % 3, l = (j + 2) % 3;
+        o[h][j] = m.C0[0] * es[j] + m.C0[1] * (es[k] + es[l]) + d11 * (es[j] - m.ebar[j]) +
+                  d12 * (es[k] + es[l] - m.ebar[k] - m.ebar[l]);
+      }
+      o[h][3] = d11;
+      o[h][4] = d12;
+      o[h][5] = d44;
+    }
+#pragma unroll
+    for (int f = 0; f < 6; ++f) out[f * npair + bf + t * RG::TL] = mk(o[0][f], o[1][f]);
+  }
+}
+
+// Polarisation rows from the real strain r6 and the per-point coefficients
+// lc6 (k_el_local), r2c of each of the six tensor components into e6.  Fields
+// are addressed as a uniform base plus a 32-bit pair index.
+template <int M, int RB>
+__global__ void __launch_bounds__((RowGeo<M, RB>::THREADS))
+k_el_tau(const double* __restrict__ lc6, const double* __restrict__ r6, cx<double>* __restrict__ e6, Geo g,
+         const cx<double>* twN, const cx<double>* twM) {
   using RG = RowGeo<M, RB>;
   __shared__ cx<double> lds[RB * RG::LD];
   const int rl = threadIdx.x / RG::TL;
@@ -262,46 +322,33 @@ k_el_tau(const cx<double>* __restrict__ st, const double* __restrict__ r6, cx<do
   const long long rr = rvalid ? row : 0;
   const long long rb = rr * g.P;
   const long long npair = (long long)nrows * M;
-  const cx<double>* s6 = reinterpret_cast<const cx<double>*>(r6) + rr * M;
-  cx<double> th[3][RG::R0];
-  row_eta3<M, RB>(st, rb, rvalid, th, bf, rbuf, twN, twM, g);
-#pragma unroll
-  for (int v = 0; v < 3; ++v)
-#pragma unroll
-    for (int t = 0; t < RG::R0; ++t) th[v][t] = mk(hfun(th[v][t].re), hfun(th[v][t].im));
+  const cx<double>* s6 = reinterpret_cast<const cx<double>*>(r6);
+  const cx<double>* lc = reinterpret_cast<const cx<double>*>(lc6);
+  const uint32_t q0 = (uint32_t)(rr * M) + bf;
+  // rows past the end read row 0 (rr = 0; in bounds) and store nothing
+  auto ld = [&](const cx<double>* f, uint32_t q) { return at32(f, q); };
 #pragma unroll 1
-  for (int c = 0; c < 6; ++c) {
+  for (int c = 0; c < 3; ++c) {
+    const int k = c == 2 ? 0 : c + 1, l = c == 0 ? 2 : c - 1;
     cx<double> a[RG::R0];
 #pragma unroll
     for (int t = 0; t < RG::R0; ++t) {
-      const int q = bf + t * RG::TL;
-      double out[2];
+      const uint32_t q = q0 + t * RG::TL;
+      const cx<double> A = ld(lc + c * npair, q), d11 = ld(lc + 3 * npair, q), d12 = ld(lc + 4 * npair, q);
+      const cx<double> uj = ld(s6 + c * npair, q), uk = ld(s6 + k * npair, q), ul = ld(s6 + l * npair, q);
+      a[t] = mk(A.re - d11.re * uj.re - d12.re * (uk.re + ul.re), A.im - d11.im * uj.im - d12.im * (uk.im + ul.im));
+      if (t % 4 == 3) __builtin_amdgcn_sched_barrier(0);  // four points' loads in flight at a time
+    }
+    row_r2c<double, M, RB>(a, e6 + c * g.fs + rb, rvalid, bf, rbuf, twN, twM);
+  }
+#pragma unroll 1
+  for (int c = 3; c < 6; ++c) {
+    cx<double> a[RG::R0];
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const double t0 = h ? th[0][t].im : th[0][t].re;
-        const double t1 = h ? th[1][t].im : th[1][t].re;
-        const double t2 = h ? th[2][t].im : th[2][t].re;
-        const Cubic C = local_stiffness(m, t0 + t1 + t2);
-        const double d11 = C.c11 - m.C0[0], d12 = C.c12 - m.C0[1], d44 = C.c44 - m.C0[2];
-        double r = 0.0;
-        if (c < 3) {
-          double es[3];
-          eigen_diag(m, t0, t1, t2, es);
-          double d[3];
-#pragma unroll
-          for (int i = 0; i < 3; ++i) {
-            const cx<double> e = rvalid ? s6[i * npair + q] : mk(0.0, 0.0);
-            d[i] = m.ebar[i] + (h ? e.im : e.re) - es[i];
-          }
-          const int j = c, k1 = (c + 1) % 3, k2 = (c + 2) % 3;
-          r = m.C0[0] * es[j] + m.C0[1] * (es[k1] + es[k2]) - (d11 * d[j] + d12 * (d[k1] + d[k2]));
-        } else {
-          const cx<double> e = rvalid ? s6[c * npair + q] : mk(0.0, 0.0);
-          r = -2.0 * d44 * (h ? e.im : e.re);
-        }
-        out[h] = r;
-      }
-      a[t] = mk(out[0], out[1]);
+    for (int t = 0; t < RG::R0; ++t) {
+      const uint32_t q = q0 + t * RG::TL;
+      const cx<double> d44 = ld(lc + 5 * npair, q), u = ld(s6 + c * npair, q);
+      a[t] = mk(-2.0 * d44.re * u.re, -2.0 * d44.im * u.im);
     }
     row_r2c<double, M, RB>(a, e6 + c * g.fs + rb, rvalid, bf, rbuf, twN, twM);
   }

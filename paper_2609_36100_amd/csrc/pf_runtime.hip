@@ -372,12 +372,12 @@ static bool launch_xpass_c2r(pf_ctx* c, const cx<double>* in, double* re, int nf
 // ---- per-kernel-class timing --------------------------------------------------
 enum KClass {
   KC_STAGE = 0, KC_YFFT, KC_THETA, KC_ELASTIC, KC_DRIVE, KC_ZFWD_AC, KC_FINAL,
-  KC_XR2C, KC_XC2R, KC_ZFFT, KC_EL_K, KC_EL_TAU, KC_EL_STRAIN, KC_EL_DRIVE, KC_COUNT
+  KC_XR2C, KC_XC2R, KC_ZFFT, KC_EL_K, KC_EL_TAU, KC_EL_STRAIN, KC_EL_DRIVE, KC_EL_LOCAL, KC_COUNT
 };
 static const char* const kc_names[KC_COUNT] = {
     "stage_invz", "ypass", "xpass_theta", "zpass_elastic", "xpass_drive",
     "zpass_fwd_ac", "finalize", "xpass_r2c", "xpass_c2r", "zpass",
-    "el_kspace", "el_tau", "el_strain", "el_drive"};
+    "el_kspace", "el_tau", "el_strain", "el_drive", "el_local"};
 
 static void prof_begin(pf_ctx* c) {
   if (!c->prof_on) return;
@@ -428,7 +428,9 @@ static bool launch_el_rows(pf_ctx* c, const cx<double>* T1, cx<double>* out, dou
     if constexpr (K == 0)
       k_el_strain<M, RB><<<nb, blk, 0, c->stream>>>(c->E6, c->R6, g, twN, twM, mx);
     else if constexpr (K == 1)
-      k_el_tau<M, RB><<<nb, blk, 0, c->stream>>>(T1, c->R6, c->E6, g, c->mk, twN, twM);
+      k_el_tau<M, RB><<<nb, blk, 0, c->stream>>>(c->LC6, c->R6, c->E6, g, twN, twM);
+    else if constexpr (K == 4)
+      k_el_local<M, RB><<<nb, blk, 0, c->stream>>>(T1, c->LC6, g, c->mk, twN, twM);
     else if constexpr (K == 2)
       k_el_drive<M, RB><<<nb, blk, 0, c->stream>>>(T1, c->R6, out, g, c->mk, twN, twM);
     else
@@ -482,12 +484,15 @@ static pf_status el_solve(pf_ctx* c, cx<double>* T1, cx<double>* FE0, int accumu
   prof_begin(c);
   k_el_start<<<kgrid, 256, 0, c->stream>>>(T3, c->E6, FE0, accumulate, g, c->mk);
   prof_end(c, KC_EL_K, (9.0 + (FE0 ? (accumulate ? 2 : 1) : 0)) * fk);
+  prof_begin(c);
+  ok = ok && launch_el_rows<4>(c, T1, nullptr, nullptr);
+  prof_end(c, KC_EL_LOCAL, 3 * fk + 6 * fr);
   back(nullptr);
   int it = 0;
   while (ok && it < c->p.el_max_iter) {
     prof_begin(c);
     ok = ok && launch_el_rows<1>(c, T1, nullptr, nullptr);
-    prof_end(c, KC_EL_TAU, 9 * fk + 6 * fr);  // eta rows, the strain (normal parts re-read from cache)
+    prof_end(c, KC_EL_TAU, 6 * fk + 12 * fr);  // coefficients and strain read, six spectra written
     prof_begin(c);
     ok = ok && launch_colfft<double, -1, 1>(c, c->E6, c->E6, 6, 1.0);
     prof_end(c, KC_YFFT, 12 * fk);
@@ -899,6 +904,7 @@ void pf_finalize(pf_ctx* c) {
   hipFree(c->ycopy);
   hipFree(c->E6);
   hipFree(c->R6);
+  hipFree(c->LC6);
   hipFree(c->elmax);
   hipFree(c->el_part);
   for (int i = 0; i < 6; ++i) {
@@ -962,6 +968,7 @@ pf_status pf_init(const pf_params* p, void* stream, pf_ctx** out) {
   if (s == PF_OK && c->norm_real) s = dalloc(c, (void**)&c->ycopy, kbytes64);
   if (s == PF_OK && c->inhom) s = dalloc(c, (void**)&c->E6, sizeof(cx<double>) * 6 * (size_t)g.fs);
   if (s == PF_OK && c->inhom) s = dalloc(c, (void**)&c->R6, sizeof(double) * 6 * (size_t)g.nx * g.ny * g.nz);
+  if (s == PF_OK && c->inhom) s = dalloc(c, (void**)&c->LC6, sizeof(double) * 6 * (size_t)g.nx * g.ny * g.nz);
   if (s == PF_OK && c->inhom) s = dalloc(c, (void**)&c->elmax, sizeof(double));
   if (s == PF_OK && c->inhom) s = dalloc(c, (void**)&c->el_part, sizeof(double) * (size_t)el_row_blocks(c));
   for (int i = 0; i < c->tab.s && s == PF_OK; ++i) {
