@@ -351,11 +351,14 @@ class Integrator:
         finite = bool(np.all(np.isfinite(y_new))) and np.isfinite(err)
         return y_new, (err if finite else np.inf)
 
-    def advance(self, y, t, t_final, dt_sequence=None):
-        """Integrate from t to t_final; returns (y, t).  Replays ``dt_sequence`` if given."""
+    def advance(self, y, t, t_final, dt_sequence=None, max_steps=None):
+        """Integrate from t to t_final; returns (y, t).  Replays ``dt_sequence`` if given;
+        stops after ``max_steps`` accepted steps if given."""
         rejects = 0
+        accepted = 0
         seq = list(dt_sequence) if dt_sequence is not None else None
-        while t < t_final * (1.0 - 1e-15) and (seq is None or seq):
+        while (t < t_final * (1.0 - 1e-15) and (seq is None or seq)
+               and (max_steps is None or accepted < max_steps)):
             dt = seq.pop(0) if seq is not None else min(self.dt, self.dt_max)
             dt = min(dt, t_final - t)
             y_new, err = self.attempt(y, dt)
@@ -370,6 +373,7 @@ class Integrator:
             self.stats["log"].append((t, dt, err, bool(ok), self.dt))
             if ok:
                 y, t = y_new, t + dt
+                accepted += 1
                 self.stats["steps"] += 1
                 self.stats["dts"].append(dt)
                 self.stats["errs"].append(err)
