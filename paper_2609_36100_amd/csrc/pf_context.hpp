@@ -229,8 +229,8 @@ struct pf_ctx {
   std::vector<hipEvent_t> prof_ev;
   size_t prof_used = 0;
   std::vector<std::pair<int, double>> prof_pending;  // (class, algorithmic bytes)
-  double prof_ms[16] = {0}, prof_bytes[16] = {0};
-  int64_t prof_n[16] = {0};
+  double prof_ms[24] = {0}, prof_bytes[24] = {0};
+  int64_t prof_n[24] = {0};
 
   int64_t ws_bytes = 0;
   double t = 0.0;

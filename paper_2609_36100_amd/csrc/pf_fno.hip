@@ -84,12 +84,14 @@ struct LineTerm {
 
 // ---- channel-mixing GEMM: Out[p][n] = epi(sum_k In[p][k] Bt[n][k] [+ line term]) ----
 // K % 4 == 0 (zero beyond K), P % 128 == 0, N <= 32 * NT.  Epilogue: + bias[n] + resid[p][n],
-// stores any of: f32 result, bf16 pre-activation, bf16 GELU(pre).
+// times GELU'(gpre[p][n]) (a data gradient through the activation), stores any
+// of: f32 result, bf16 pre-activation, bf16 GELU(pre).
 template <int NT>
 __global__ void __launch_bounds__(256)
 k_cm_gemm(const u16* __restrict__ In, int ldin, int K, const u16* __restrict__ Bt, int N,
           const float* __restrict__ bias, const float* __restrict__ resid, int ldres, float* __restrict__ outf,
-          u16* __restrict__ outpre, u16* __restrict__ outact, int ldout, int accumulate, LineTerm lt) {
+          u16* __restrict__ outpre, u16* __restrict__ outact, int ldout, int accumulate, LineTerm lt,
+          const u16* __restrict__ gpre) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const long long p0 = ((long long)blockIdx.x * 4 + wave) * 32;
   const int lr = lane & 31, lg = lane >> 5;
@@ -151,6 +153,7 @@ k_cm_gemm(const u16* __restrict__ In, int ldin, int K, const u16* __restrict__ B
       float v = acc[t][i] + bb;
       if (resid) v += resid[row * ldres + col];
       const long long o = row * ldout + col;
+      if (gpre) v *= gelu_g(bf2f(gpre[o]));
       if (outf) outf[o] = accumulate ? outf[o] + v : v;
       if (outpre) outpre[o] = f2bf(v);
       if (outact) outact[o] = f2bf(gelu_f(v));
@@ -589,8 +592,8 @@ struct pf_fno {
   u16 *A1 = nullptr, *A2 = nullptr, *A3 = nullptr, *Tb = nullptr, *B3 = nullptr, *B2 = nullptr;
   float *T = nullptr, *B1 = nullptr, *outf = nullptr;
   // backward buffers
-  float *dvf = nullptr, *dvf2 = nullptr, *dpref = nullptr, *dT = nullptr, *dhf = nullptr;
-  u16 *dvb = nullptr, *dpreb = nullptr, *douthb = nullptr, *dhb = nullptr, *dSb = nullptr;
+  float *dvf = nullptr, *dvf2 = nullptr, *dpref = nullptr, *dpref2 = nullptr, *dT = nullptr, *dhf = nullptr;
+  u16 *dvb = nullptr, *dpreb = nullptr, *dpreb2 = nullptr, *douthb = nullptr, *dhb = nullptr, *dSb = nullptr;
   float* part = nullptr;
   long long part_elems = 0;
   double* dpart = nullptr;
@@ -715,7 +718,7 @@ static void lm(pf_fno* F, const u16* G, int R, int K, const u16* X, long long xb
 
 static void cm_launch(pf_fno* F, long long points, const u16* In, int ldin, int K, const u16* Bt, int N,
                       const float* bias, const float* resid, int ldres, float* outf, u16* outpre, u16* outact,
-                      int ldout, int accumulate, const LineTerm& lt) {
+                      int ldout, int accumulate, const LineTerm& lt, const u16* gpre = nullptr) {
   const unsigned grid = (unsigned)(points / 128);
   double bytes = cm_bytes((double)points, K, N, bias, resid, outf, outpre, outact, accumulate);
   double flops = 2.0 * points * K * N;
@@ -723,19 +726,20 @@ static void cm_launch(pf_fno* F, long long points, const u16* In, int ldin, int 
     bytes += 2.0 * lt.R * lt.K + (double)(points / lt.R) * lt.K * N * 2.0;
     flops += 2.0 * points * lt.K * N;
   }
+  if (gpre) bytes += points * N * 2.0;
   account(F, FK_CM, bytes, flops);
   if (N <= 32)
     k_cm_gemm<1><<<grid, 256, 0, F->stream>>>(In, ldin, K, Bt, N, bias, resid, ldres, outf, outpre, outact, ldout,
-                                               accumulate, lt);
+                                               accumulate, lt, gpre);
   else
     k_cm_gemm<4><<<grid, 256, 0, F->stream>>>(In, ldin, K, Bt, N, bias, resid, ldres, outf, outpre, outact, ldout,
-                                               accumulate, lt);
+                                               accumulate, lt, gpre);
 }
 
 static void cm(pf_fno* F, const u16* In, int ldin, int K, const u16* Bt, int N, const float* bias, const float* resid,
                int ldres, float* outf, u16* outpre, u16* outact, int ldout, int accumulate,
-               const LineTerm& lt = LineTerm()) {
-  cm_launch(F, F->P, In, ldin, K, Bt, N, bias, resid, ldres, outf, outpre, outact, ldout, accumulate, lt);
+               const LineTerm& lt = LineTerm(), const u16* gpre = nullptr) {
+  cm_launch(F, F->P, In, ldin, K, Bt, N, bias, resid, ldres, outf, outpre, outact, ldout, accumulate, lt, gpre);
 }
 
 constexpr int kWgradBlocks = 512;  // blocks (point chunks) of one weight-gradient reduction
@@ -862,19 +866,14 @@ static void backward(pf_fno* F) {
   float* g = F->gr;
   // projection: out = hact P2 + c2
   wgrad(F, F->hact, h, h, F->dvf2, co, co, g + F->o_P2, g + F->o_c2);
-  cm(F, F->douthb, F->coutp, F->coutp, F->bP2, h, nullptr, nullptr, 0, F->dhf, nullptr, nullptr, h, 0);
-  account(F, FK_GELU, (double)P * h * (4.0 + 2.0 + 4.0 + 2.0), 20.0 * P * h);
-  k_gelu_bwd<<<gdiv(P * h, 256), 256, 0, F->stream>>>(F->dhf, F->hpre, F->dhf, F->dhb, P * h, 0);
+  // d hpre = (d out P2^T) GELU'(hpre), formed in the GEMM's epilogue
+  cm(F, F->douthb, F->coutp, F->coutp, F->bP2, h, nullptr, nullptr, 0, F->dhf, F->dhb, nullptr, h, 0, LineTerm(),
+     F->hpre);
   wgrad(F, F->pre[c.layers - 1], w, w, F->dhf, h, h, g + F->o_P1, g + F->o_c1);
-  cm(F, F->dhb, h, h, F->bP1, w, nullptr, nullptr, 0, F->dvf, nullptr, nullptr, w, 0);
   const int Nz = m2 * m * w;
-  for (int l = c.layers - 1; l >= 0; --l) {
-    const bool last = l == c.layers - 1;
-    account(F, FK_GELU, (double)P * w * (4.0 + 2.0 + 4.0 + 2.0), 20.0 * P * w);
-    k_gelu_bwd<<<gdiv(P * w, 256), 256, 0, F->stream>>>(F->dvf, F->pre[l], F->dpref, F->dpreb, P * w, last ? 1 : 0);
-    wgrad(F, F->v[l], w, w, F->dpref, w, w, g + F->o_W[l], g + F->o_b[l]);
-    // spectral path: transposes of the inverse stages
-    lm(F, F->GxiT, 2 * m, n, F->dpreb, (long long)n * w, w, w, n * n, nullptr, F->B2, (long long)2 * m * w, w, 0);
+  // the spectral path's transposed stages from dpreb (bf16 d pre of the layer) down to A1
+  auto spectral_back = [&](int l, const u16* dpreb) {
+    lm(F, F->GxiT, 2 * m, n, dpreb, (long long)n * w, w, w, n * n, nullptr, F->B2, (long long)2 * m * w, w, 0);
     lm(F, F->GyiT, 2 * m2, 2 * n, F->B2, (long long)2 * n * m * w, m * w, m * w, n, nullptr, F->B3,
        (long long)2 * m2 * m * w, m * w, 0);
     lm(F, F->GziT, 2 * m2, 2 * n, F->B3, 0, Nz, Nz, 1, F->dT, nullptr, 0, Nz, 0);
@@ -886,21 +885,46 @@ static void backward(pf_fno* F) {
         F->S[l], F->dT, g + F->o_Rr[l], g + F->o_Ri[l], F->mode_count, w);
     k_mix_bwd_data<<<gdiv((long long)F->mode_count * w, 256), 256, 0, F->stream>>>(F->dT, F->bRr[l], F->bRi[l],
                                                                                    F->dSb, F->mode_count, w);
-    // transposes of the forward stages: z, y (batch z), x (batch z,y); accumulate into dv
     lm(F, F->GzfT, 2 * n, 2 * m2, F->dSb, 0, Nz, Nz, 1, nullptr, F->A2, 0, Nz, 0);
     lm(F, F->GyfT, 2 * n, 2 * m2, F->A2, (long long)2 * m2 * m * w, m * w, m * w, n, nullptr, F->A1,
        (long long)2 * n * m * w, m * w, 0);
-    // pointwise data gradient plus the transposed x stage of the spectral path
-    if (F->fuse_x) {
-      LineTerm lt;
-      lt.G = F->GxfT;
-      lt.K = 2 * m;
-      lt.R = n;
-      lt.X = F->A1;
-      lt.xbs = (long long)2 * m * w;
-      lt.ldx = w;
-      cm(F, F->dpreb, w, w, F->bW[l], w, nullptr, nullptr, 0, F->dvf, nullptr, nullptr, w, 0, lt);
-    } else {
+  };
+  if (F->fuse_x) {
+    // d v_l = d pre_l W^T + (transposed x stage of A1) in one GEMM, whose
+    // epilogue applies GELU'(pre_{l-1}) to give d pre_{l-1} (f32 and bf16),
+    // ping-ponging between two buffers; the last layer is linear
+    LineTerm lt;
+    lt.G = F->GxfT;
+    lt.K = 2 * m;
+    lt.R = n;
+    lt.X = F->A1;
+    lt.xbs = (long long)2 * m * w;
+    lt.ldx = w;
+    float* df[2] = {F->dpref, F->dpref2};
+    u16* db[2] = {F->dpreb, F->dpreb2};
+    int cur = 0;
+    cm(F, F->dhb, h, h, F->bP1, w, nullptr, nullptr, 0, df[cur], db[cur], nullptr, w, 0);
+    for (int l = c.layers - 1; l >= 0; --l) {
+      wgrad(F, F->v[l], w, w, df[cur], w, w, g + F->o_W[l], g + F->o_b[l]);
+      spectral_back(l, db[cur]);
+      if (l > 0) {
+        cm(F, db[cur], w, w, F->bW[l], w, nullptr, nullptr, 0, df[1 - cur], db[1 - cur], nullptr, w, 0, lt,
+           F->pre[l - 1]);
+        cur = 1 - cur;
+      } else {
+        cm(F, db[cur], w, w, F->bW[0], w, nullptr, nullptr, 0, F->dvf, nullptr, nullptr, w, 0, lt);
+      }
+    }
+  } else {
+    cm(F, F->dhb, h, h, F->bP1, w, nullptr, nullptr, 0, F->dvf, nullptr, nullptr, w, 0);
+    for (int l = c.layers - 1; l >= 0; --l) {
+      const bool last = l == c.layers - 1;
+      account(F, FK_GELU, (double)P * w * (4.0 + 2.0 + 4.0 + 2.0), 20.0 * P * w);
+      k_gelu_bwd<<<gdiv(P * w, 256), 256, 0, F->stream>>>(F->dvf, F->pre[l], F->dpref, F->dpreb, P * w,
+                                                          last ? 1 : 0);
+      wgrad(F, F->v[l], w, w, F->dpref, w, w, g + F->o_W[l], g + F->o_b[l]);
+      spectral_back(l, F->dpreb);
+      // pointwise data gradient plus the transposed x stage of the spectral path
       cm(F, F->dpreb, w, w, F->bW[l], w, nullptr, nullptr, 0, F->dvf, nullptr, nullptr, w, 0);
       lm(F, F->GxfT, n, 2 * m, F->A1, (long long)2 * m * w, w, w, n * n, F->dvf, nullptr, (long long)n * w, w, 1);
     }
@@ -999,6 +1023,8 @@ pf_status pf_fno_create(const pf_fno_config* cfg, void* stream, pf_fno** out) {
   A((void**)&F->dhf, 4 * P * h);
   A((void**)&F->dhb, 2 * P * h);
   A((void**)&F->dpreb, 2 * P * w);
+  if (F->fuse_x) A((void**)&F->dpref2, 4 * P * w);
+  if (F->fuse_x) A((void**)&F->dpreb2, 2 * P * w);
   A((void**)&F->douthb, 2 * P * F->coutp);
   A((void**)&F->dSb, 2 * spec);
   F->part_elems = (long long)kWgradBlocks * (std::max(std::max(w, h), 8) + 1) * std::max(std::max(w, h), 8);

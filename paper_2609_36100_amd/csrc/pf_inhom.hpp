@@ -23,8 +23,9 @@
 //   k_el_start        theta~ -> Gamma0 C0 eps*(theta~) into E6, F^E_c
 //   x_el_local        T1 eta -> LC6 (the polarisation's per-point coefficients)
 //   z, y inverse (6) -> x_el_strain        R6 = eps_u
-//   repeat:  x_el_tau (LC6, R6 -> E6), y, z forward (6), k_el_gamma (E6),
-//            z, y inverse (6), x_el_strain (E6 -> R6, largest change)
+//   repeat:  x_el_tau (LC6, R6 -> E6), y forward (6), k_el_zgamma (z forward,
+//            Gamma0, z inverse), y inverse (6), x_el_strain (E6 -> R6, largest
+//            change)
 //   x_el_drive (T1, R6 -> T3 g) -> y forward, z forward to F^E_eta
 #pragma once
 
@@ -148,31 +149,6 @@ __global__ void __launch_bounds__(256) k_el_start(const cx<double>* th, cx<doubl
   }
 }
 
-// One update, per mode: e6 (the polarisation's spectrum) <- Gamma0 e6, in place.
-__global__ void __launch_bounds__(256) k_el_gamma(cx<double>* e6, Geo g, ModelK m) {
-  const long long nrow = (long long)g.nz * g.ny;
-  const long long total = nrow * g.nxh;
-  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
-       i += (long long)gridDim.x * blockDim.x) {
-    const int x = (int)(i % g.nxh);
-    const long long row = i / g.nxh;
-    const int y = (int)(row % g.ny), z = (int)(row / g.ny);
-    const long long idx = row * g.P + x;
-    cx<double> tau[6], eps[6];
-#pragma unroll
-    for (int c = 0; c < 6; ++c) tau[c] = e6[c * g.fs + idx];
-    double n[3];
-    if (deriv_normal(g, x, y, z, n)) {
-      gamma0_apply(m, n, tau, eps);
-    } else {
-#pragma unroll
-      for (int c = 0; c < 6; ++c) eps[c] = mk(0.0, 0.0);
-    }
-#pragma unroll
-    for (int c = 0; c < 6; ++c) e6[c * g.fs + idx] = eps[c];
-  }
-}
-
 // Non-negative doubles order like their bit patterns: a block's largest change
 // is merged into *mx with an integer atomic max.
 __device__ inline void atomic_max_nonneg(double* mx, double v) {
@@ -182,6 +158,63 @@ __device__ inline void atomic_max_nonneg(double* mx, double v) {
 __global__ void k_el_zero(double* p) { *p = 0.0; }
 
 }  // namespace
+
+// One update's Green-operator step fused with its z transforms, per column
+// of TX consecutive kx at one y: forward z-FFT of the six polarisation
+// spectra (after their forward y pass), eps~ = Gamma0(n) tau~ per mode,
+// inverse z-FFT times `scale`, in place.  The six fields of a column stay in
+// registers between the transforms (radix-4 ends keep them at four values per
+// field and thread); columns past nxh transform zeros and store nothing.
+template <int N, int TX, int RE>
+__global__ void __launch_bounds__((ColGeo<N, TX, RE>::THREADS))
+k_el_zgamma(cx<double>* __restrict__ e6, Geo g, ModelK m, const cx<double>* twz, double scale) {
+  using CG = ColGeo<N, TX, RE>;
+  __shared__ cx<double> lds[N * CG::LD];
+  __shared__ cx<double> twl[N];
+  for (int j = threadIdx.x; j < N; j += CG::THREADS) twl[j] = twz[j];
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int nbx = (g.nxh + TX - 1) / TX;
+  const int xb = tile % nbx, y = tile / nbx;
+  const int col = threadIdx.x % TX, bf = threadIdx.x / TX;
+  const int x = xb * TX + col;
+  const bool valid = x < g.nxh;
+  const uint32_t lstride = (uint32_t)(g.ny * g.P);
+  const uint32_t base = (uint32_t)(y * g.P + x);
+  auto buf = [&](int pos) -> cx<double>& { return lds[pos * CG::LD + col]; };
+  cx<double> a[6][CG::R0];
+#pragma unroll
+  for (int c = 0; c < 6; ++c)
+#pragma unroll
+    for (int t = 0; t < CG::R0; ++t)
+      a[c][t] = valid ? at32(e6 + c * g.fs, base + (bf + t * CG::TL) * lstride) : mk(0.0, 0.0);
+#pragma unroll
+  for (int c = 0; c < 6; ++c) line_fft<double, N, -1, RE, true>(a[c], bf, twl, buf, true);
+#pragma unroll
+  for (int t = 0; t < CG::R0; ++t) {
+    const int z = bf + t * CG::TL;
+    double nv[3];
+    cx<double> tau[6], eps[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) tau[c] = a[c][t];
+    if (valid && deriv_normal(g, x, y, z, nv)) {
+      gamma0_apply(m, nv, tau, eps);
+    } else {
+#pragma unroll
+      for (int c = 0; c < 6; ++c) eps[c] = mk(0.0, 0.0);
+    }
+#pragma unroll
+    for (int c = 0; c < 6; ++c) a[c][t] = scale * eps[c];
+    __builtin_amdgcn_sched_barrier(0);  // one mode at a time
+  }
+#pragma unroll
+  for (int c = 0; c < 6; ++c) {
+    line_fft<double, N, +1, RE, true>(a[c], bf, twl, buf, true);
+    if (valid) {
+#pragma unroll
+      for (int t = 0; t < CG::R0; ++t) at32(e6 + c * g.fs, base + (bf + t * CG::TL) * lstride) = a[c][t];
+    }
+  }
+}
 
 // Real strain rows from the six inverse-transformed spectra (c2r of each row),
 // written to r6 (pitch nx per row, field stride nx ny nz); with mx, the

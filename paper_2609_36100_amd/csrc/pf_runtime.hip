@@ -372,12 +372,12 @@ static bool launch_xpass_c2r(pf_ctx* c, const cx<double>* in, double* re, int nf
 // ---- per-kernel-class timing --------------------------------------------------
 enum KClass {
   KC_STAGE = 0, KC_YFFT, KC_THETA, KC_ELASTIC, KC_DRIVE, KC_ZFWD_AC, KC_FINAL,
-  KC_XR2C, KC_XC2R, KC_ZFFT, KC_EL_K, KC_EL_TAU, KC_EL_STRAIN, KC_EL_DRIVE, KC_EL_LOCAL, KC_COUNT
+  KC_XR2C, KC_XC2R, KC_ZFFT, KC_EL_K, KC_EL_TAU, KC_EL_STRAIN, KC_EL_DRIVE, KC_EL_LOCAL, KC_EL_ZGAMMA, KC_COUNT
 };
 static const char* const kc_names[KC_COUNT] = {
     "stage_invz", "ypass", "xpass_theta", "zpass_elastic", "xpass_drive",
     "zpass_fwd_ac", "finalize", "xpass_r2c", "xpass_c2r", "zpass",
-    "el_kspace", "el_tau", "el_strain", "el_drive", "el_local"};
+    "el_kspace", "el_tau", "el_strain", "el_drive", "el_local", "el_zgamma"};
 
 static void prof_begin(pf_ctx* c) {
   if (!c->prof_on) return;
@@ -437,6 +437,21 @@ static bool launch_el_rows(pf_ctx* c, const cx<double>* T1, cx<double>* out, dou
       k_el_energy<M, RB><<<nb, blk, 0, c->stream>>>(T1, c->R6, g, c->mk, twN, twM, c->el_part);
   });
 }
+// Columns per work-group of the fused Green-operator z pass: at least 64
+// threads, at least two columns.
+constexpr int el_ztx(int n) { return line_threads(n, 4) >= 32 ? 2 : 64 / line_threads(n, 4); }
+
+static bool launch_el_zgamma(pf_ctx* c, double scale) {
+  const Geo& g = c->g;
+  return col_dispatch(g.nz, [&](auto NC) {
+    constexpr int N = decltype(NC)::value;
+    constexpr int TX = el_ztx(N);
+    const int nbx = (g.nxh + TX - 1) / TX;
+    k_el_zgamma<N, TX, 4><<<dim3(nbx * g.ny), dim3(ColGeo<N, TX, 4>::THREADS), 0, c->stream>>>(
+        c->E6, g, c->mk, tw<double>(c, 0), scale);
+  });
+}
+
 static int el_row_blocks(const pf_ctx* c) {
   int nb = 0;
   row_dispatch(c->g.nx / 2, [&](auto MC) {
@@ -461,10 +476,13 @@ static pf_status el_solve(pf_ctx* c, cx<double>* T1, cx<double>* FE0, int accumu
   const int kgrid = (int)std::min<long long>((modes + 255) / 256, 16384);
   const double s = c->mk.inv_n3;
   bool ok = true;
-  auto back = [&](double* mx) {  // E6 spectra -> R6 real strain
-    prof_begin(c);
-    ok = ok && launch_colfft<double, +1, 2>(c, c->E6, c->E6, 6, s);
-    prof_end(c, KC_ZFFT, 12 * fk);
+  // E6 spectra -> R6 real strain (the z inverse only with `zinv`)
+  auto back = [&](double* mx, bool zinv) {
+    if (zinv) {
+      prof_begin(c);
+      ok = ok && launch_colfft<double, +1, 2>(c, c->E6, c->E6, 6, s);
+      prof_end(c, KC_ZFFT, 12 * fk);
+    }
     prof_begin(c);
     ok = ok && launch_colfft<double, +1, 1>(c, c->E6, c->E6, 6, 1.0);
     prof_end(c, KC_YFFT, 12 * fk);
@@ -487,7 +505,7 @@ static pf_status el_solve(pf_ctx* c, cx<double>* T1, cx<double>* FE0, int accumu
   prof_begin(c);
   ok = ok && launch_el_rows<4>(c, T1, nullptr, nullptr);
   prof_end(c, KC_EL_LOCAL, 3 * fk + 6 * fr);
-  back(nullptr);
+  back(nullptr, true);
   int it = 0;
   while (ok && it < c->p.el_max_iter) {
     prof_begin(c);
@@ -496,14 +514,12 @@ static pf_status el_solve(pf_ctx* c, cx<double>* T1, cx<double>* FE0, int accumu
     prof_begin(c);
     ok = ok && launch_colfft<double, -1, 1>(c, c->E6, c->E6, 6, 1.0);
     prof_end(c, KC_YFFT, 12 * fk);
+    // forward z, Gamma0 and the scaled inverse z in one pass
     prof_begin(c);
-    ok = ok && launch_colfft<double, -1, 2>(c, c->E6, c->E6, 6, 1.0);
-    prof_end(c, KC_ZFFT, 12 * fk);
-    prof_begin(c);
-    k_el_gamma<<<kgrid, 256, 0, c->stream>>>(c->E6, g, c->mk);
-    prof_end(c, KC_EL_K, 12 * fk);
+    ok = ok && launch_el_zgamma(c, s);
+    prof_end(c, KC_EL_ZGAMMA, 12 * fk);
     k_el_zero<<<1, 1, 0, c->stream>>>(c->elmax);
-    back(c->elmax);
+    back(c->elmax, false);
     ++it;
     if (!ok) break;
     PF_HIP(hipMemcpyAsync(&c->host_red[6], c->elmax, sizeof(double), hipMemcpyDeviceToHost, c->stream));
