@@ -431,7 +431,7 @@ pf_status pf_fno_work(pf_fno* f, int32_t enable, double* bytes, double* flops, i
  * [batch][cin][n^3]; nexts may equal states): one network pass whose GEMMs
  * run over every sample's points and lines together, so each sample's result
  * is bit-identical to pf_fno_apply's.  The batched activations (about
- * 1.2 GB per 128^3 sample at width 32, hidden 128) are allocated on the
+ * 0.93 GB per 128^3 sample at width 32, hidden 128) are allocated on the
  * first call and grown when a larger batch comes.  Errors: PF_ERR_ARG (batch
  * < 1, NULL, cin != cout), PF_ERR_OOM, PF_ERR_HIP. */
 pf_status pf_fno_apply_batch(pf_fno* f, const double* states, double* nexts, int32_t batch);
