@@ -164,9 +164,11 @@ k_cm_gemm(const u16* __restrict__ In, int ldin, int K, const u16* __restrict__ B
 // ---- small-matrix GEMM: Out_b[r][n] = sum_k G[r][k] X_b[k][n] ---------------
 // G row-major R x K (K % 4 == 0, zero beyond K), X_b rows of stride ldx,
 // batch stride xbs.
-// Each wave owns 32 columns and 4 row tiles (128 rows) per pass.  A block's
-// four waves cover wpb column groups of `bpb = 4 / wpb` batches (wpb = 1 for
-// the 32-column x stages, so no wave of a block idles there).
+// Each wave owns 32 columns and 4 row tiles (128 rows); blockIdx.z picks the
+// 128-row band, so stages with many rows (the inverse stages: 2n rows) spread
+// over more waves.  A block's four waves cover wpb column groups of
+// `bpb = 4 / wpb` batches (wpb = 1 for the 32-column x stages, so no wave of a
+// block idles there).
 __global__ void __launch_bounds__(256)
 k_lm_gemm(const u16* __restrict__ G, int R, int K, const u16* __restrict__ X, long long xbs, int ldx, int Nc,
           float* __restrict__ outf, u16* __restrict__ outb, long long obs, int ldo, int accumulate, int wpb,
@@ -178,7 +180,8 @@ k_lm_gemm(const u16* __restrict__ G, int R, int K, const u16* __restrict__ X, lo
   const int n = (blockIdx.x * wpb + wave % wpb) * 32 + lr;
   const bool valid = n < Nc;
   const u16* Xb = X + b * xbs;
-  for (int r0 = 0; r0 < R; r0 += 128) {
+  {
+    const int r0 = blockIdx.z * 128;
     f32x16 acc[4];
 #pragma unroll
     for (int t = 0; t < 4; ++t)
@@ -708,12 +711,17 @@ static double cm_bytes(double points, int K, int N, const float* bias, const flo
 static void lm(pf_fno* F, const u16* G, int R, int K, const u16* X, long long xbs, int ldx, int Nc, int batches,
                float* outf, u16* outb, long long obs, int ldo, int accumulate) {
   const int wpb = Nc <= 32 ? 1 : (Nc <= 64 ? 2 : 4);  // waves per batch
-  dim3 grid(gdiv(Nc, 32 * wpb), gdiv(batches, 4 / wpb));
   const double cols = (double)Nc * batches;
   account(F, FK_LM, 2.0 * R * K + 2.0 * K * cols + (outf ? (accumulate ? 8.0 : 4.0) : 2.0) * R * cols,
           2.0 * R * K * cols);
-  k_lm_gemm<<<grid, 256, 0, F->stream>>>(G, R, K, X, xbs, ldx, Nc, outf, outb, obs, ldo, accumulate, wpb,
-                                         (long long)batches);
+  // the batches in launches of at most 65535 blocks along y
+  const long long per = 65535LL * (4 / wpb);
+  for (long long b0 = 0; b0 < batches; b0 += per) {
+    const long long nb = std::min<long long>(per, batches - b0);
+    dim3 grid(gdiv(Nc, 32 * wpb), gdiv(nb, 4 / wpb), gdiv(R, 128));
+    k_lm_gemm<<<grid, 256, 0, F->stream>>>(G, R, K, X + b0 * xbs, xbs, ldx, Nc, outf ? outf + b0 * obs : nullptr,
+                                           outb ? outb + b0 * obs : nullptr, obs, ldo, accumulate, wpb, nb);
+  }
 }
 
 static void cm_launch(pf_fno* F, long long points, const u16* In, int ldin, int K, const u16* Bt, int N,
