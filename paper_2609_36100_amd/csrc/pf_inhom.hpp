@@ -167,7 +167,7 @@ __global__ void k_el_zero(double* p) { *p = 0.0; }
 // field and thread); columns past nxh transform zeros and store nothing.
 template <int N, int TX, int RE>
 __global__ void __launch_bounds__((ColGeo<N, TX, RE>::THREADS))
-k_el_zgamma(cx<double>* __restrict__ e6, Geo g, ModelK m, const cx<double>* twz, double scale) {
+__attribute__((amdgpu_waves_per_eu(3))) k_el_zgamma(cx<double>* __restrict__ e6, Geo g, ModelK m, const cx<double>* twz, double scale) {
   using CG = ColGeo<N, TX, RE>;
   __shared__ cx<double> lds[N * CG::LD];
   __shared__ cx<double> twl[N];
@@ -175,43 +175,78 @@ k_el_zgamma(cx<double>* __restrict__ e6, Geo g, ModelK m, const cx<double>* twz,
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int nbx = (g.nxh + TX - 1) / TX;
   const int xb = tile % nbx, y = tile / nbx;
-  const int col = threadIdx.x % TX, bf = threadIdx.x / TX;
-  const int x = xb * TX + col;
-  const bool valid = x < g.nxh;
   const uint32_t lstride = (uint32_t)(g.ny * g.P);
-  const uint32_t base = (uint32_t)(y * g.P + x);
-  auto buf = [&](int pos) -> cx<double>& { return lds[pos * CG::LD + col]; };
+  // thread-derived indices, rebuilt at each phase from an opaque copy of the
+  // thread index so that they (and the addresses made from them) are not held
+  // across the per-mode solves
+  struct Ix {
+    int col, bf, x;
+    uint32_t base;
+    bool valid;
+  };
+  auto ix = [&]() {
+    int tq = (int)threadIdx.x;
+    asm volatile("" : "+v"(tq));
+    Ix r;
+    r.col = tq % TX;
+    r.bf = tq / TX;
+    r.x = xb * TX + r.col;
+    r.valid = r.x < g.nxh;
+    r.base = (uint32_t)(y * g.P + r.x);
+    return r;
+  };
   cx<double> a[6][CG::R0];
+  {
+    const Ix I = ix();
 #pragma unroll
-  for (int c = 0; c < 6; ++c)
+    for (int c = 0; c < 6; ++c)
 #pragma unroll
-    for (int t = 0; t < CG::R0; ++t)
-      a[c][t] = valid ? at32(e6 + c * g.fs, base + (bf + t * CG::TL) * lstride) : mk(0.0, 0.0);
-#pragma unroll
-  for (int c = 0; c < 6; ++c) line_fft<double, N, -1, RE, true>(a[c], bf, twl, buf, true);
-#pragma unroll
-  for (int t = 0; t < CG::R0; ++t) {
-    const int z = bf + t * CG::TL;
-    double nv[3];
-    cx<double> tau[6], eps[6];
-#pragma unroll
-    for (int c = 0; c < 6; ++c) tau[c] = a[c][t];
-    if (valid && deriv_normal(g, x, y, z, nv)) {
-      gamma0_apply(m, nv, tau, eps);
-    } else {
-#pragma unroll
-      for (int c = 0; c < 6; ++c) eps[c] = mk(0.0, 0.0);
-    }
-#pragma unroll
-    for (int c = 0; c < 6; ++c) a[c][t] = scale * eps[c];
-    __builtin_amdgcn_sched_barrier(0);  // one mode at a time
+      for (int t = 0; t < CG::R0; ++t)
+        a[c][t] = I.valid ? at32(e6 + c * g.fs, I.base + (I.bf + t * CG::TL) * lstride) : mk(0.0, 0.0);
   }
 #pragma unroll
   for (int c = 0; c < 6; ++c) {
-    line_fft<double, N, +1, RE, true>(a[c], bf, twl, buf, true);
-    if (valid) {
+    const Ix I = ix();
+    line_fft<double, N, -1, RE, true>(a[c], I.bf, twl, [&](int pos) -> cx<double>& { return lds[pos * CG::LD + I.col]; },
+                                      true);
+  }
+  // the spectra are final here (the compiler would otherwise finish the last
+  // butterflies inside the per-mode loop and hold their inputs as well)
 #pragma unroll
-      for (int t = 0; t < CG::R0; ++t) at32(e6 + c * g.fs, base + (bf + t * CG::TL) * lstride) = a[c][t];
+  for (int c = 0; c < 6; ++c)
+#pragma unroll
+    for (int t = 0; t < CG::R0; ++t) pin(a[c][t]);
+  {
+    const Ix I = ix();
+#pragma unroll
+    for (int t = 0; t < CG::R0; ++t) {
+      const int z = I.bf + t * CG::TL;
+      double nv[3];
+      cx<double> tau[6], eps[6];
+#pragma unroll
+      for (int c = 0; c < 6; ++c) tau[c] = a[c][t];
+      if (I.valid && deriv_normal(g, I.x, y, z, nv)) {
+        gamma0_apply(m, nv, tau, eps);
+      } else {
+#pragma unroll
+        for (int c = 0; c < 6; ++c) eps[c] = mk(0.0, 0.0);
+      }
+#pragma unroll
+      for (int c = 0; c < 6; ++c) {
+        a[c][t] = scale * eps[c];
+        pin(a[c][t]);
+      }
+      __builtin_amdgcn_sched_barrier(0);  // one mode at a time
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 6; ++c) {
+    const Ix I = ix();
+    line_fft<double, N, +1, RE, true>(a[c], I.bf, twl, [&](int pos) -> cx<double>& { return lds[pos * CG::LD + I.col]; },
+                                      true);
+    if (I.valid) {
+#pragma unroll
+      for (int t = 0; t < CG::R0; ++t) at32(e6 + c * g.fs, I.base + (I.bf + t * CG::TL) * lstride) = a[c][t];
     }
   }
 }

@@ -247,6 +247,11 @@ __device__ inline int xcd_tile(int b, int nb) {
 template <typename T>
 __device__ inline cx<T> ld(const cx<T>* p) { return *p; }
 
+// Marks a value as computed at this point: the compiler may not move its
+// arithmetic below here (an empty asm that reads and rewrites the registers).
+template <typename T>
+__device__ inline void pin(cx<T>& z) { asm volatile("" : "+v"(z.re), "+v"(z.im)); }
+
 // Element i of an array at f, addressed as a uniform base plus a 32-bit byte
 // offset: one field of the largest supported grid (512^3, row pitch 264) is
 // 1.1 GB, so in-field offsets fit, and the compiler then keeps one VGPR per
@@ -636,74 +641,109 @@ __device__ inline void body_zpass_elastic(cx<T>* th, const Geo& g, const ModelK&
   const int nbx = (g.nxh + TX - 1) / TX;
   const int xb = tile % nbx;
   const int y = tile / nbx;
-  const int col = tid % TX;
-  const int bf = tid / TX;
-  const int x = xb * TX + col;
-  const bool valid = act && x < g.nxh;
   const uint32_t lstride = (uint32_t)(g.ny * g.P);
-  const uint32_t base = (uint32_t)(y * g.P + x);
-  auto buf = [&](int pos) -> cx<T>& { return lds[pos * CG::LD + col]; };
+  // Thread-derived indices, rebuilt at each phase from an opaque copy of tid:
+  // the compiler then recomputes them (and the LDS and global addresses made
+  // from them) where they are used instead of holding them across the solve.
+  struct Ix {
+    int col, bf, x;
+    uint32_t base;
+    bool valid;
+  };
+  auto ix = [&]() {
+    int tq = tid;
+    asm volatile("" : "+v"(tq));
+    Ix r;
+    r.col = tq % TX;
+    r.bf = tq / TX;
+    r.x = xb * TX + r.col;
+    r.valid = act && r.x < g.nxh;
+    r.base = (uint32_t)(y * g.P + r.x);
+    return r;
+  };
   cx<T> a[3][CG::R0];
   // All three fields are loaded before the first transform.  With LB the
   // transforms synchronise with LDS-only barriers (twz then points to LDS), so
   // the loads of fields 1 and 2 stay in flight while field 0 is transformed,
   // and the stores of the inverse transforms overlap the next one.
+  {
+    const Ix I = ix();
 #pragma unroll
-  for (int v = 0; v < 3; ++v) {
-#pragma unroll
-    for (int t = 0; t < CG::R0; ++t) {
-      const int z = bf + t * CG::TL;
-      a[v][t] = valid ? at32(th + v * g.fs, base + z * lstride) : mk<T>(0, 0);
-    }
-  }
-#pragma unroll
-  for (int v = 0; v < 3; ++v) line_fft<T, N, -1, RE, LB>(a[v], bf, twz, buf, act);
-  const T kx = (T)(x * g.kfx);
-  const T ky = (T)(mode_of(y, g.ny) * g.kfy);
-#pragma unroll
-  for (int t = 0; t < CG::R0; ++t) {
-    const int z = bf + t * CG::TL;
-    const T kz = (T)(mode_of(z, g.nz) * g.kfz);
-    cx<T> thv[3] = {a[0][t], a[1][t], a[2][t]};
-    cx<T> e[3];
-    const bool k0 = (x == 0) && (y == 0) && (z == 0);
-    if (k0) {
-#pragma unroll
-      for (int v = 0; v < 3; ++v) {
-        cx<T> acc = mk<T>((T)m.hom[v], 0);
-#pragma unroll
-        for (int w = 0; w < 3; ++w) acc = acc + (T)m.B0[v][w] * thv[w];
-        e[v] = acc;
-      }
-    } else {
-      elastic_apply<T>(m, kx, ky, kz, thv, e);
-    }
-    if (valid) {
-      const T k2 = kx * kx + ky * ky + kz * kz;
-      cx<T> Hs = thv[0] + thv[1] + thv[2];
-      cx<T> fe = ((T)m.fEc * k2) * Hs;
-      const uint32_t idx = base + z * lstride;
-      if (accumulate) {
-        cx<TE> old = at32(FEc, idx);
-        at32(FEc, idx) = mk<TE>((TE)(old.re + fe.re), (TE)(old.im + fe.im));
-      } else {
-        at32(FEc, idx) = mk<TE>((TE)fe.re, (TE)fe.im);
-      }
-    }
-    const T s = (T)m.inv_n3;
-#pragma unroll
-    for (int v = 0; v < 3; ++v) a[v][t] = s * e[v];
-    // one mode at a time: interleaving the solves only raises register pressure
-    __builtin_amdgcn_sched_barrier(0);
-  }
-#pragma unroll
-  for (int v = 0; v < 3; ++v) {
-    line_fft<T, N, +1, RE, LB>(a[v], bf, twz, buf, act);
-    if (valid) {
+    for (int v = 0; v < 3; ++v) {
 #pragma unroll
       for (int t = 0; t < CG::R0; ++t) {
-        const int z = bf + t * CG::TL;
-        at32(th + v * g.fs, base + z * lstride) = a[v][t];
+        const int z = I.bf + t * CG::TL;
+        a[v][t] = I.valid ? at32(th + v * g.fs, I.base + z * lstride) : mk<T>(0, 0);
+      }
+    }
+  }
+#pragma unroll
+  for (int v = 0; v < 3; ++v) {
+    const Ix I = ix();
+    auto buf = [&](int pos) -> cx<T>& { return lds[pos * CG::LD + I.col]; };
+    line_fft<T, N, -1, RE, LB>(a[v], I.bf, twz, buf, act);
+  }
+  // Every spectrum value is final here: left alone, the compiler sinks the
+  // second half of the last butterflies past the first mode's solve and holds
+  // their inputs as well.
+#pragma unroll
+  for (int v = 0; v < 3; ++v)
+#pragma unroll
+    for (int t = 0; t < CG::R0; ++t) pin(a[v][t]);
+  {
+    const Ix I = ix();
+    const T kx = (T)(I.x * g.kfx);
+    const T ky = (T)(mode_of(y, g.ny) * g.kfy);
+#pragma unroll
+    for (int t = 0; t < CG::R0; ++t) {
+      const int z = I.bf + t * CG::TL;
+      const T kz = (T)(mode_of(z, g.nz) * g.kfz);
+      cx<T> thv[3] = {a[0][t], a[1][t], a[2][t]};
+      cx<T> e[3];
+      const bool k0 = (I.x == 0) && (y == 0) && (z == 0);
+      if (k0) {
+#pragma unroll
+        for (int v = 0; v < 3; ++v) {
+          cx<T> acc = mk<T>((T)m.hom[v], 0);
+#pragma unroll
+          for (int w = 0; w < 3; ++w) acc = acc + (T)m.B0[v][w] * thv[w];
+          e[v] = acc;
+        }
+      } else {
+        elastic_apply<T>(m, kx, ky, kz, thv, e);
+      }
+      if (I.valid) {
+        const T k2 = kx * kx + ky * ky + kz * kz;
+        cx<T> Hs = thv[0] + thv[1] + thv[2];
+        cx<T> fe = ((T)m.fEc * k2) * Hs;
+        const uint32_t idx = I.base + z * lstride;
+        if (accumulate) {
+          cx<TE> old = at32(FEc, idx);
+          at32(FEc, idx) = mk<TE>((TE)(old.re + fe.re), (TE)(old.im + fe.im));
+        } else {
+          at32(FEc, idx) = mk<TE>((TE)fe.re, (TE)fe.im);
+        }
+      }
+      const T s = (T)m.inv_n3;
+#pragma unroll
+      for (int v = 0; v < 3; ++v) {
+        a[v][t] = s * e[v];
+        pin(a[v][t]);
+      }
+      // one mode at a time: interleaving the solves only raises register pressure
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+#pragma unroll
+  for (int v = 0; v < 3; ++v) {
+    const Ix I = ix();
+    auto buf = [&](int pos) -> cx<T>& { return lds[pos * CG::LD + I.col]; };
+    line_fft<T, N, +1, RE, LB>(a[v], I.bf, twz, buf, act);
+    if (I.valid) {
+#pragma unroll
+      for (int t = 0; t < CG::R0; ++t) {
+        const int z = I.bf + t * CG::TL;
+        at32(th + v * g.fs, I.base + z * lstride) = a[v][t];
       }
     }
   }
