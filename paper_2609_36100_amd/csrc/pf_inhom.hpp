@@ -167,7 +167,7 @@ __global__ void k_el_zero(double* p) { *p = 0.0; }
 // field and thread); columns past nxh transform zeros and store nothing.
 template <int N, int TX, int RE>
 __global__ void __launch_bounds__((ColGeo<N, TX, RE>::THREADS))
-__attribute__((amdgpu_waves_per_eu(3))) k_el_zgamma(cx<double>* __restrict__ e6, Geo g, ModelK m, const cx<double>* twz, double scale) {
+k_el_zgamma(cx<double>* __restrict__ e6, Geo g, ModelK m, const cx<double>* twz, double scale) {
   using CG = ColGeo<N, TX, RE>;
   __shared__ cx<double> lds[N * CG::LD];
   __shared__ cx<double> twl[N];
