@@ -284,8 +284,11 @@ pf_status pf_profile_get(pf_ctx* ctx, int32_t cls, double* total_ms, int64_t* la
  * derivative arrays (call it between steps, never inside one) and leaves the
  * state untouched.  pf_tuning_set forces a variant (PF_ERR_ARG for one that
  * does not exist for this grid); pf_tuning_ms returns the last timing of a
- * variant (0 if never timed).  Kinds are 0 .. pf_tuning_kinds()-1;
- * pf_tuning_name never returns NULL ("" for an invalid kind). */
+ * variant (0 if never timed).  pf_tuning_get reports the variant in use,
+ * its kx columns per work-group and the first (= last) radix of the z-line
+ * plan that kind's kernel runs on this grid.  Kinds are
+ * 0 .. pf_tuning_kinds()-1; pf_tuning_name never returns NULL ("" for an
+ * invalid kind). */
 pf_status pf_autotune(pf_ctx* ctx, int32_t reps);
 int32_t pf_tuning_kinds(void);
 const char* pf_tuning_name(int32_t kind);

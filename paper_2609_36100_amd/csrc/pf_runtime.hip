@@ -74,9 +74,12 @@ static bool row_supported(int m) {
 // variant 1 twice that.  Small lines get wider tiles so a work-group has at
 // least one full wavefront; lines shorter than 64 have only variant 0.
 static const char* const ck_names[CK_COUNT] = {"colfft", "stage_invz", "zpass_elastic", "zpass_fwd_ac"};
-// The elastic pass holds three fields in registers, so it uses radix-4 ends
-// (half the registers per field) and narrower tiles.
-constexpr int col_re(int kind) { return kind == CK_ELASTIC ? 4 : 8; }
+// Largest end radix of each kind's line plan.  The elastic pass holds three
+// fields in registers, so it takes narrower tiles and its ends stay at radix 4
+// where 16 divides the line length (half the registers per field of radix 8);
+// lines that 36 divides but 16 does not (504) take radix-6 ends, since the
+// radix-3 ends they would otherwise get cost the pass a quarter more time.
+constexpr int col_re(int kind) { return kind == CK_ELASTIC ? 6 : 8; }
 constexpr int col_tx(int n, int kind, int elem_bytes, int v) {
   const int seg = (kind == CK_ELASTIC ? 32 : 64) << ((n >= 64) ? v : 0);
   int tx = seg / elem_bytes;
@@ -1473,7 +1476,7 @@ pf_status pf_tuning_get(pf_ctx* c, int32_t kind, int32_t* variant, int32_t* tile
   const int eb = c->mixed ? (int)sizeof(cx<float>) : (int)sizeof(cx<double>);
   if (variant) *variant = v;
   if (tile_cols) *tile_cols = col_tx(c->g.nz, kind, eb, v ? 1 : 0);
-  if (end_radix) *end_radix = col_re(kind);
+  if (end_radix) *end_radix = plan(c->g.nz, col_re(kind)).r[0];
   if (ms_v0) *ms_v0 = c->tune_ms[kind][0];
   if (ms_v1) *ms_v1 = c->tune_ms[kind][1];
   return PF_OK;

@@ -1,5 +1,5 @@
 """Grids with a factor 7 (the paper's 168^3, 336^3 and 504^3 runs): radix-7
-butterflies in the line FFTs, radix-2 line ends for 504 = 2 * 252 and the
+butterflies in the line FFTs, radix-6 line ends for 504 = 6 * 84 and the
 tile-width cap that keeps those work-groups within 1024 threads, against the
 FP64 CPU oracle on identical seeded inputs.
 
@@ -140,6 +140,29 @@ def test_mixed_precision_rhs_factor7(torch, params):
             assert _rel(gE[f], FE[f]) < 1e-4, (f, _rel(gE[f], FE[f]))
         else:
             assert float(np.max(np.abs(gE[f]))) < 1e-4
+
+
+@pytest.mark.parametrize("variant", [0, 1])
+def test_mixed_precision_rhs_504_lines(torch, params, variant):
+    """The precision form with 504-point z lines (radix-6 line ends in every
+    column pass, the elastic one included) in both tile variants: the implicit
+    part within 1e-10, the explicit part within the stated 1e-4 per field."""
+    shape = (504, 24, 16)
+    _say("mixed rhs", shape, "variant", variant)
+    c, eta = _rand_fields(shape, seed=77)
+    m = om.Model(shape, params)
+    y = om.to_kspace(c, eta)
+    for _ in range(5):   # smooth the random fields (oracle IMEX Euler)
+        y, _, _ = oark.ark_step(y, 0.05, oark.imex_euler(), m.f_explicit, m.implicit_symbol())
+    FI, FE = m.rhs(y)
+    with _solver(shape, params, precision="mixed") as s:
+        for k in range(4):
+            s.set_tuning(k, variant)
+        fI, fE = s.rhs(s.kspace_from_numpy(y))
+        gI, gE = s.kspace_to_numpy(fI), s.kspace_to_numpy(fE)
+    for f in range(4):
+        assert _rel(gI[f], FI[f]) < TOL, ("FI", f, _rel(gI[f], FI[f]))
+        assert _rel(gE[f], FE[f]) < 1e-4, ("FE", f, _rel(gE[f], FE[f]))
 
 
 def _band_limited_state(n):
