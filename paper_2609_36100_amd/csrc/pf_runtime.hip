@@ -74,20 +74,25 @@ static bool row_supported(int m) {
 // variant 1 twice that.  Small lines get wider tiles so a work-group has at
 // least one full wavefront; lines shorter than 64 have only variant 0.
 static const char* const ck_names[CK_COUNT] = {"colfft", "stage_invz", "zpass_elastic", "zpass_fwd_ac"};
-// Largest end radix of each kind's line plan.  The elastic pass holds three
-// fields in registers, so it takes narrower tiles and its ends stay at radix 4
-// where 16 divides the line length (half the registers per field of radix 8);
-// lines that 36 divides but 16 does not (504) take radix-6 ends, since the
-// radix-3 ends they would otherwise get cost the pass a quarter more time.
-constexpr int col_re(int kind) { return kind == CK_ELASTIC ? 6 : 8; }
+// Largest end radix of each kind's line plan (elem_bytes: 16 FP64, 8 FP32
+// complex values).  The FP64 elastic pass holds three fields in registers, so
+// it takes narrower tiles and its ends stay at radix 4 where 16 divides the
+// line length (half the registers per field of radix 8; radix 8 gained
+// nothing at 512^3); lines that 36 divides but 16 does not (504) take radix-6
+// ends, since the radix-3 ends they would otherwise get cost the pass a
+// quarter more time.  In FP32 the three fields fit at radix 8 (113 VGPRs at
+// 512: 8-column tiles ran 1.03 ms against 1.43 ms for 4-column radix-4 ones).
+constexpr int col_re(int kind, int elem_bytes = 16) {
+  return kind != CK_ELASTIC ? 8 : elem_bytes == 8 ? 8 : 6;
+}
 constexpr int col_tx(int n, int kind, int elem_bytes, int v) {
   const int seg = (kind == CK_ELASTIC ? 32 : 64) << ((n >= 64) ? v : 0);
   int tx = seg / elem_bytes;
   if (tx < 1) tx = 1;
-  while (tx * line_threads(n, col_re(kind)) < 64 && tx < 16) tx *= 2;
+  while (tx * line_threads(n, col_re(kind, elem_bytes)) < 64 && tx < 16) tx *= 2;
   // long lines with small end radices (504 in the elastic pass: 168 threads
   // per line) stay within 1024 threads per work-group
-  while (tx > 1 && tx * line_threads(n, col_re(kind)) > 1024) tx /= 2;
+  while (tx > 1 && tx * line_threads(n, col_re(kind, elem_bytes)) > 1024) tx /= 2;
   return tx;
 }
 // Whether the wave-specialised column FFT (variant 2 of "colfft") exists for
@@ -302,7 +307,7 @@ static bool launch_zpass_elastic(pf_ctx* c, cx<T>* th, cx<TE>* FEc, int accumula
   return col_dispatch(g.nz, [&](auto NC) {
     constexpr int N = decltype(NC)::value;
     with_variant(c->var[CK_ELASTIC], [&](auto VC) {
-      constexpr int RE = col_re(CK_ELASTIC);
+      constexpr int RE = col_re(CK_ELASTIC, sizeof(cx<T>));
       constexpr int TX = col_tx(N, CK_ELASTIC, sizeof(cx<T>), decltype(VC)::value);
       const int nbx = (g.nxh + TX - 1) / TX;
       k_zpass_elastic<T, TE, N, TX, RE><<<dim3(nbx * g.ny), dim3(ColGeo<N, TX, RE>::THREADS), 0, c->stream>>>(
@@ -1476,7 +1481,7 @@ pf_status pf_tuning_get(pf_ctx* c, int32_t kind, int32_t* variant, int32_t* tile
   const int eb = c->mixed ? (int)sizeof(cx<float>) : (int)sizeof(cx<double>);
   if (variant) *variant = v;
   if (tile_cols) *tile_cols = col_tx(c->g.nz, kind, eb, v ? 1 : 0);
-  if (end_radix) *end_radix = plan(c->g.nz, col_re(kind)).r[0];
+  if (end_radix) *end_radix = plan(c->g.nz, col_re(kind, eb)).r[0];
   if (ms_v0) *ms_v0 = c->tune_ms[kind][0];
   if (ms_v1) *ms_v1 = c->tune_ms[kind][1];
   return PF_OK;

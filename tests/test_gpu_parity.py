@@ -301,17 +301,18 @@ def test_ark2_ark3_adaptive_replay_and_decisions(torch, params, method):
 
 
 @pytest.mark.parametrize("variant", [0, 1])
-@pytest.mark.parametrize("n", [32, 64])
+@pytest.mark.parametrize("n", [32, 64, 128])
 def test_mixed_precision_rhs_error_bound(torch, params, n, variant):
     """FP32 FFT / pointwise / elastic work against the FP64 oracle: stated bound
-    1e-4 per field, for both tile variants of every column pass."""
+    1e-4 per field, for both tile variants of every column pass (the FP32
+    elastic pass has radix-4 line ends at 32, radix-8 ones at 64 and 128)."""
     _say("mixed rhs", n, "variant", variant)
     spec, c, eta = pfinputs.config("twin64", n=n)
     m = om.Model((n, n, n), params)
     y = om.to_kspace(c, eta)
     # the sharp initial nuclei have eta in {0, 1} exactly, where the AC force
     # vanishes identically; diffuse the interfaces first (oracle IMEX Euler)
-    for _ in range(20):
+    for _ in range(20 if n <= 64 else 5):
         y, _, _ = oark.ark_step(y, 0.05, oark.imex_euler(), m.f_explicit, m.implicit_symbol())
     FI, FE = m.rhs(y)
     with _solver(n, params, precision="mixed") as s:
