@@ -115,6 +115,13 @@ static void with_variant(int v, F&& f) {
 }
 // Rows per row-pass work-group: about 256 threads.
 constexpr int rb_of(int m) { return line_threads(m) >= 256 ? 1 : 256 / line_threads(m); }
+// Rows per work-group of the stage cycle's theta and drive passes: 128
+// threads where the line's thread count divides 128 (their drive pass ran
+// 9-16 % faster so, their FP64 theta pass 3-8 %, at 512^3 and 256^3), else
+// the general rule (lines of 42 or 84 threads would leave part-filled waves).
+constexpr int rb_x(int m) {
+  return line_threads(m) <= 128 && 128 % line_threads(m) == 0 ? 128 / line_threads(m) : rb_of(m);
+}
 
 #define PF_HIP(call)                                   \
   do {                                                 \
@@ -336,7 +343,7 @@ static bool launch_xpass_theta(pf_ctx* c, const cx<T>* st, cx<T>* th) {
   const Geo& g = c->g;
   return row_dispatch(g.nx / 2, [&](auto MC) {
     constexpr int M = decltype(MC)::value;
-    constexpr int RB = rb_of(M);
+    constexpr int RB = rb_x(M);
     const int nrows = g.nz * g.ny;
     k_xpass_theta<T, M, RB><<<dim3((nrows + RB - 1) / RB), dim3(RowGeo<M, RB>::THREADS), 0, c->stream>>>(
         st, th, g, tw<T>(c, 3), tw<T>(c, 2));
@@ -348,7 +355,7 @@ static bool launch_xpass_drive(pf_ctx* c, const cx<T>* st, cx<T>* el) {
   const Geo& g = c->g;
   return row_dispatch(g.nx / 2, [&](auto MC) {
     constexpr int M = decltype(MC)::value;
-    constexpr int RB = rb_of(M);
+    constexpr int RB = rb_x(M);
     const int nrows = g.nz * g.ny;
     k_xpass_drive<T, M, RB><<<dim3((nrows + RB - 1) / RB), dim3(RowGeo<M, RB>::THREADS), 0, c->stream>>>(
         st, el, g, c->mk, tw<T>(c, 3), tw<T>(c, 2));
