@@ -165,6 +165,24 @@ def test_mixed_precision_rhs_504_lines(torch, params, variant):
         assert _rel(gE[f], FE[f]) < 1e-4, ("FE", f, _rel(gE[f], FE[f]))
 
 
+@pytest.mark.parametrize("shape,precision,expect", [
+    ((64, 64, 64), "fp64", dict(colfft=8, stage_invz=8, zpass_elastic=4, zpass_fwd_ac=8)),
+    ((64, 64, 64), "mixed", dict(colfft=8, stage_invz=8, zpass_elastic=8, zpass_fwd_ac=8)),
+    ((504, 24, 16), "fp64", dict(colfft=6, stage_invz=6, zpass_elastic=6, zpass_fwd_ac=6)),
+    ((504, 24, 16), "mixed", dict(colfft=6, stage_invz=6, zpass_elastic=6, zpass_fwd_ac=6)),
+    ((56, 56, 56), "fp64", dict(colfft=2, stage_invz=2, zpass_elastic=2, zpass_fwd_ac=2)),
+])
+def test_tuning_reports_the_z_line_end_radix(torch, params, shape, precision, expect):
+    """pf_tuning_get reports the first (= last) radix of the z-line plan each
+    column-pass kind runs: radix-8 ends where 64 divides the length (radix 4
+    for the FP64 elastic pass, which holds three fields per thread), radix-6
+    ends at 504 = 6 * 84 in every kind, radix 2 at 56."""
+    _say("tuning end radix", shape, precision)
+    with _solver(shape, params, precision=precision) as s:
+        got = {k: v["end_radix"] for k, v in s.tuning().items()}
+    assert got == expect, got
+
+
 def _band_limited_state(n):
     """Cosines with wavevector components 0 or +-1 (units of 2 pi / L): every
     product the right-hand side forms (degree <= 9 in the fields) stays below
