@@ -310,8 +310,13 @@ template <int M, int RB>
 __device__ inline void row_eta3(const cx<double>* st, long long rb, bool rvalid, cx<double> (*et)[RowGeo<M, RB>::R0],
                                 int bf, cx<double>* rbuf, const cx<double>* twN, const cx<double>* twM,
                                 const Geo& g) {
-#pragma unroll 1
-  for (int v = 0; v < 3; ++v) row_c2r<double, M, RB>(st + (1 + v) * g.fs + rb, rvalid, et[v], bf, rbuf, twN, twM);
+  // unrolled (a loop over v would index et at run time and put it in scratch
+  // memory), one transform at a time
+#pragma unroll
+  for (int v = 0; v < 3; ++v) {
+    row_c2r<double, M, RB>(st + (1 + v) * g.fs + rb, rvalid, et[v], bf, rbuf, twN, twM);
+    __builtin_amdgcn_sched_barrier(0);
+  }
 }
 
 // The per-point coefficients of the polarisation, once per solve: with
@@ -508,8 +513,11 @@ k_el_drive(const cx<double>* __restrict__ st, const double* __restrict__ r6, cx<
 #pragma unroll
     for (int v = 0; v < 3; ++v) et[v][t] = mk(gv[v][0], gv[v][1]);
   }
-#pragma unroll 1
-  for (int v = 0; v < 3; ++v) row_r2c<double, M, RB>(et[v], el + v * g.fs + rb, rvalid, bf, rbuf, twN, twM);
+#pragma unroll
+  for (int v = 0; v < 3; ++v) {
+    row_r2c<double, M, RB>(et[v], el + v * g.fs + rb, rvalid, bf, rbuf, twN, twM);
+    __builtin_amdgcn_sched_barrier(0);
+  }
 }
 
 // Elastic energy density sums, 1/2 sigma : (eps_bar + eps_u - eps*) over the
