@@ -435,7 +435,10 @@ static bool launch_el_rows(pf_ctx* c, const cx<double>* T1, cx<double>* out, dou
   const Geo& g = c->g;
   return row_dispatch(g.nx / 2, [&](auto MC) {
     constexpr int M = decltype(MC)::value;
-    constexpr int RB = rb_of(M);
+    // 128-thread groups for the drive and local-coefficient kernels (0.64 ->
+    // 0.58 ms and 0.27 -> 0.26 ms at 256^3), 256-thread ones for the strain
+    // kernel (5 % slower at 128), the update and the energy sums
+    constexpr int RB = (K == 2 || K == 4) ? rb_x(M) : rb_of(M);
     const int nb = (g.nz * g.ny + RB - 1) / RB;
     const dim3 blk(RowGeo<M, RB>::THREADS);
     const cx<double>* twN = tw<double>(c, 3);
@@ -475,7 +478,7 @@ static int el_row_blocks(const pf_ctx* c) {
   int nb = 0;
   row_dispatch(c->g.nx / 2, [&](auto MC) {
     constexpr int M = decltype(MC)::value;
-    nb = (c->g.nz * c->g.ny + rb_of(M) - 1) / rb_of(M);
+    nb = (c->g.nz * c->g.ny + rb_of(M) - 1) / rb_of(M);  // the energy kernel's groups
   });
   return nb;
 }
